@@ -1,0 +1,167 @@
+/*
+ * fpe.h — C ABI of the MI355X (gfx950) Fast Polynomial Evaluator library.
+ *
+ * The library implements the evaluation phase of the Fast Polynomial Evaluator
+ * (FPE) of Anton, Mihalache and Vigneron, "Fast evaluation of real and complex
+ * polynomials" (arXiv 2211.06320): many points z against one preconditioned
+ * complex polynomial P(z) = a_0 + a_1 z + ... + a_d z^d.
+ *
+ * Conventions shared by every entry point:
+ *   - Complex numbers are interleaved (re, im) pairs of IEEE binary64, the
+ *     memory layout of C99 double complex and of torch.complex128.
+ *   - Coefficients are ordered a_0 first (the paper's CSV convention, Section 8.1).
+ *   - Arguments named *_dev are device pointers on the current HIP device;
+ *     arguments named *_host are host pointers.  The library never allocates
+ *     device memory: the caller provides every device buffer, including the
+ *     workspaces sized by the *_workspace_size queries.
+ *   - Values are returned as P(z) = m 2^e with m a complex double whose larger
+ *     component lies in [1/2, 1) (or m = 0, e = 0) and e a 64-bit integer: the
+ *     paper's number model has unbounded exponents (Section 2.2), and at the
+ *     sizes this library targets |P(z)| routinely exceeds the FP64 range.
+ *   - Every call returns an fpe_status; FPE_OK is 0.  Nothing is printed and no
+ *     exception crosses the ABI.  fpe_last_error() gives a thread-local detail
+ *     string for the last failing call on the calling thread.
+ *   - Work is enqueued on the given stream.  Only fpe_precondition waits for
+ *     the stream (it builds the concave cover on the host); fpe_eval and
+ *     fpe_horner_eval only enqueue and return.
+ */
+#ifndef FPE_H
+#define FPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fpe_status;
+
+enum {
+    FPE_OK = 0,
+    FPE_ERR_INVALID_ARG = 1,   /* NULL pointer, negative size, bad flag         */
+    FPE_ERR_NONFINITE = 2,     /* a coefficient is NaN or infinite               */
+    FPE_ERR_PRECISION = 3,     /* p_bits outside 1..53                           */
+    FPE_ERR_WORKSPACE = 4,     /* workspace smaller than the size query's answer */
+    FPE_ERR_HIP = 5,           /* a HIP runtime call failed                      */
+    FPE_ERR_UNSUPPORTED = 6    /* input outside the supported range (see below)  */
+};
+
+/* Opaque handle of a preconditioned polynomial.  The handle lives in host
+   memory; its tables live in the caller's precondition workspace, which must
+   stay allocated and unmodified for the handle's lifetime. */
+typedef struct fpe_plan_s *fpe_plan_t;
+
+/* Human-readable name of a status code (static storage). */
+const char *fpe_status_string(fpe_status s);
+
+/* Detail message of the last failing call on this thread (thread-local storage;
+   "" when the last call succeeded). */
+const char *fpe_last_error(void);
+
+/* ABI version, incremented on incompatible changes. */
+int32_t fpe_abi_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Preconditioning (Algorithm A_p, first block; Section 5.1).                */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace fpe_precondition needs for a polynomial of degree
+   d (d + 1 coefficients) at precision p_bits.  flags: 0 (reserved). */
+fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits, uint32_t flags,
+                                           size_t *bytes);
+
+/* Preconditions P for precision p_bits (Algorithm A_p, preconditioning):
+ * computes the scales s(a_k) = 1 + floor(log2|a_k|) (Section 2.3), their concave
+ * cover Ehat (the least concave majorant, Section 4.1), and the good set
+ * G_p = { k : s(a_k) >= Ehat(k) - p - s(d) - 3 } (eq. threshold).
+ *
+ *   coef_dev        2 (d + 1) doubles, a_0 first; read only; may be freed once
+ *                   the call has returned.
+ *   d               degree as given, 0 <= d < 2^31 - 1.  Zero coefficients at
+ *                   either end are trimmed (the paper assumes a_0 != 0 and
+ *                   a_d != 0, Section 4.3), so s(d) uses the trimmed degree.
+ *   p_bits          1..53: the precision p of the truncation rule (53 = FP64).
+ *   flags           0 (reserved).
+ *   workspace_dev   device buffer of at least the queried size, 256-byte aligned;
+ *                   owned by the caller, borrowed by the plan.
+ *   stream          HIP stream the work is enqueued on; the call waits for it.
+ *   out_plan        receives the handle (free it with fpe_plan_destroy).
+ *
+ * Errors: FPE_ERR_INVALID_ARG (NULL pointer, d out of range, misaligned
+ * workspace), FPE_ERR_PRECISION, FPE_ERR_WORKSPACE, FPE_ERR_NONFINITE (a NaN or
+ * infinite coefficient), FPE_ERR_UNSUPPORTED (the good coefficients span more
+ * binary orders of magnitude than one FP64 window can hold: max s - min good s
+ * > 1900), FPE_ERR_HIP.  An all-zero polynomial is accepted (P == 0). */
+fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_t p_bits, uint32_t flags,
+                            void *workspace_dev, size_t workspace_bytes,
+                            hipStream_t stream, fpe_plan_t *out_plan);
+
+/* Plan summary, written to info_host[0..9]:
+ *   0 d (as given)      1 v (first nonzero index, -1 if P == 0)
+ *   2 d' (last nonzero) 3 number of cover vertices
+ *   4 |G_p|             5 T = p + s(d' - v) + 3
+ *   6 p_bits            7 chunk length C of the window kernel
+ *   8 max s(a_k)        9 minimum s(a_k) over G_p                              */
+#define FPE_PLAN_INFO_LEN 10
+fpe_status fpe_plan_info(fpe_plan_t plan, int64_t *info_host);
+
+/* Copies the cover vertices (k_i, s(a_{k_i})), increasing k, into
+ * hull_k_host / hull_s_host (capacity hull_cap entries each; at least
+ * info[3] are needed) and the good-set indicator into good_host (d + 1 bytes,
+ * 1 = k in G_p).  Any of the three pointers may be NULL to skip that table. */
+fpe_status fpe_plan_export(fpe_plan_t plan, int64_t *hull_k_host, int64_t *hull_s_host,
+                           int64_t hull_cap, uint8_t *good_host);
+
+/* Frees the host handle; the workspace stays the caller's. */
+fpe_status fpe_plan_destroy(fpe_plan_t plan);
+
+/* ------------------------------------------------------------------------- */
+/* Evaluation (Algorithm A_p, second block; Section 5.2).                    */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace fpe_eval needs for n points with this plan. */
+fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t *bytes);
+
+/* Evaluates Q_lambda(z_j) = sum over k in G_p within [l_j, r_j] of a_k z_j^k
+ * (eq. reducedQlambda) at n points, where lambda = log2|z| (eq. defLambda),
+ * N = max(Ehat + lambda Id) (eq. defN) and [l, r] is the largest integer
+ * interval on which Ehat(k) + lambda k >= N - p - s(d) - 3 (eq. def:LRN).
+ *
+ *   z_dev          2n doubles; read only.
+ *   n              number of points, 0 <= n < 2^31 (n == 0 is a no-op).
+ *   m_dev, e_dev   outputs: 2n doubles and n int64, Q_lambda(z_j) = m_j 2^{e_j}.
+ *   terms_dev      optional (NULL to skip): n int32, #(G_p within [l_j, r_j]),
+ *                  the number of terms the method keeps.
+ *   window_dev     optional (NULL to skip): 2n int64, (l_j, r_j) per point;
+ *                  l_j > r_j marks an empty window.
+ *   workspace_dev  at least fpe_eval_workspace_size bytes, 256-byte aligned.
+ *
+ * Special points: z = 0 gives a_0 (window [0, 0]); a NaN or infinite
+ * coordinate gives m = NaN, e = 0, an empty window and 0 terms; P == 0 gives
+ * m = 0, e = 0.  Concurrent calls on one plan are safe with distinct
+ * workspaces.  Errors are reported synchronously for bad arguments
+ * (FPE_ERR_INVALID_ARG, FPE_ERR_WORKSPACE) and as FPE_ERR_HIP for a failed
+ * launch. */
+fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n,
+                    double *m_dev, int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
+                    void *workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Same-GPU baseline: Horner's rule on the full polynomial (Section 1).      */
+/* ------------------------------------------------------------------------- */
+
+/* P(z_j) = sum_{k=0}^{d} a_k z_j^k by Horner's rule in FP64, one lane per point,
+ * with exact power-of-two rescaling so that the result is returned as
+ * m_j 2^{e_j} like fpe_eval.  coef_dev: 2 (d + 1) doubles, a_0 first; no
+ * workspace.  Errors: FPE_ERR_INVALID_ARG, FPE_ERR_HIP. */
+fpe_status fpe_horner_eval(const double *coef_dev, int64_t d, const double *z_dev, int64_t n,
+                           double *m_dev, int64_t *e_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPE_H */

@@ -1,0 +1,230 @@
+"""Python binding of libfpe, the MI355X Fast Polynomial Evaluator (arXiv 2211.06320).
+
+Thin ctypes marshalling over the C ABI declared in include/fpe.h: every step of
+preconditioning and evaluation runs in the HIP library; PyTorch provides device
+memory (all buffers, including workspaces, are torch tensors) and the stream.
+There is no fallback: if libfpe.so is missing, loading fails with an error.
+
+    plan = precondition(coeffs)            # coeffs: complex128 CUDA tensor, a_0 first
+    m, e = plan.eval(z)                    # P(z) ~ m * 2**e, m complex128, e int64
+    m, e, terms, window = plan.eval(z, terms=True, window=True)
+    m, e = horner_eval(coeffs, z)          # same-GPU Horner baseline
+    to_complex(m, e)                       # m * 2**e as complex128 (may overflow)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fpe.h")
+
+FPE_OK = 0
+STATUS = {0: "FPE_OK", 1: "FPE_ERR_INVALID_ARG", 2: "FPE_ERR_NONFINITE", 3: "FPE_ERR_PRECISION",
+          4: "FPE_ERR_WORKSPACE", 5: "FPE_ERR_HIP", 6: "FPE_ERR_UNSUPPORTED"}
+
+_LIB = None
+
+
+class FPEError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/fpe.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpe_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfpe.so (built by __graft_entry__.build()); raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.fpe_status_string.restype = ctypes.c_char_p
+    L.fpe_status_string.argtypes = [i32]
+    L.fpe_last_error.restype = ctypes.c_char_p
+    L.fpe_last_error.argtypes = []
+    L.fpe_abi_version.restype = i32
+    L.fpe_precondition_workspace_size.restype = i32
+    L.fpe_precondition_workspace_size.argtypes = [i64, i32, u32, P(sz)]
+    L.fpe_precondition.restype = i32
+    L.fpe_precondition.argtypes = [vp, i64, i32, u32, vp, sz, vp, P(vp)]
+    L.fpe_plan_info.restype = i32
+    L.fpe_plan_info.argtypes = [vp, P(i64)]
+    L.fpe_plan_export.restype = i32
+    L.fpe_plan_export.argtypes = [vp, P(i64), P(i64), i64, P(ctypes.c_uint8)]
+    L.fpe_plan_destroy.restype = i32
+    L.fpe_plan_destroy.argtypes = [vp]
+    L.fpe_eval_workspace_size.restype = i32
+    L.fpe_eval_workspace_size.argtypes = [vp, i64, P(sz)]
+    L.fpe_eval.restype = i32
+    L.fpe_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_horner_eval.restype = i32
+    L.fpe_horner_eval.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != FPE_OK:
+        raise FPEError(status, lib().fpe_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_complex(x, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex128 or not x.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    return x.contiguous()
+
+
+def _workspace(nbytes: int, device):
+    """Caller-owned device workspace (torch memory), 256-byte aligned."""
+    torch = _torch()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+@dataclass
+class PlanInfo:
+    d: int
+    v: int
+    dt: int
+    n_hull: int
+    n_good: int
+    T: int
+    p: int
+    chunk: int
+    s_max: int
+    s_min_good: int
+
+
+class Plan:
+    """A polynomial preconditioned by fpe_precondition (Algorithm A_p, first block)."""
+
+    def __init__(self, coeffs, p: int = 53, stream=None):
+        L = lib()
+        coeffs = _dev_complex(coeffs, "coeffs")
+        self.device = coeffs.device
+        self.d = coeffs.shape[0] - 1
+        nb = ctypes.c_size_t()
+        _check(L.fpe_precondition_workspace_size(self.d, p, 0, ctypes.byref(nb)))
+        self._ws_buf, ws = _workspace(nb.value, coeffs.device)
+        h = ctypes.c_void_p()
+        _check(L.fpe_precondition(coeffs.data_ptr(), self.d, p, 0, ws, nb.value,
+                                  _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._eval_ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fpe_plan_destroy(h)
+            self._h = None
+
+    def info(self) -> PlanInfo:
+        import numpy as np
+        out = np.zeros(10, np.int64)
+        _check(lib().fpe_plan_info(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return PlanInfo(*[int(x) for x in out])
+
+    def export(self):
+        """(hull_k, hull_s, good) as numpy arrays."""
+        import numpy as np
+        nh = self.info().n_hull
+        hk = np.zeros(max(nh, 1), np.int64)
+        hs = np.zeros(max(nh, 1), np.int64)
+        good = np.zeros(self.d + 1, np.uint8)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(lib().fpe_plan_export(self._h, hk.ctypes.data_as(i64p), hs.ctypes.data_as(i64p), max(nh, 1),
+                                     good.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return hk[:nh], hs[:nh], good.astype(bool)
+
+    def eval_workspace_bytes(self, n: int) -> int:
+        nb = ctypes.c_size_t()
+        _check(lib().fpe_eval_workspace_size(self._h, n, ctypes.byref(nb)))
+        return nb.value
+
+    def workspace(self, n: int):
+        """A cached device workspace large enough for n points."""
+        nb = self.eval_workspace_bytes(n)
+        cur = self._eval_ws.get("buf")
+        if cur is None or cur[2] < nb:
+            buf, ptr = _workspace(nb, self.device)
+            self._eval_ws["buf"] = (buf, ptr, nb)
+        return self._eval_ws["buf"][1], self._eval_ws["buf"][2]
+
+    def eval(self, z, terms: bool = False, window: bool = False, out=None, stream=None):
+        """Q_lambda(z) for every point (Algorithm A_p, second block).
+
+        Returns (m, e) or (m, e, terms, window): m complex128 [n], e int64 [n],
+        terms int32 [n] (#G_p within [l, r]), window int64 [n, 2] ((l, r)).
+        """
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        n = z.shape[0]
+        if out is None:
+            m = torch.empty(n, dtype=torch.complex128, device=z.device)
+            e = torch.empty(n, dtype=torch.int64, device=z.device)
+        else:
+            m, e = out
+        t = torch.empty(n, dtype=torch.int32, device=z.device) if terms else None
+        w = torch.empty((n, 2), dtype=torch.int64, device=z.device) if window else None
+        ws, nb = self.workspace(n)
+        _check(lib().fpe_eval(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(),
+                              t.data_ptr() if t is not None else None,
+                              w.data_ptr() if w is not None else None, ws, nb, _stream(stream)))
+        if terms or window:
+            return m, e, t, w
+        return m, e
+
+
+def precondition(coeffs, p: int = 53, stream=None) -> Plan:
+    return Plan(coeffs, p, stream)
+
+
+def horner_eval(coeffs, z, out=None, stream=None):
+    """P(z) for the full polynomial by Horner's rule on the GPU; returns (m, e)."""
+    torch = _torch()
+    coeffs = _dev_complex(coeffs, "coeffs")
+    z = _dev_complex(z, "z")
+    n = z.shape[0]
+    if out is None:
+        m = torch.empty(n, dtype=torch.complex128, device=z.device)
+        e = torch.empty(n, dtype=torch.int64, device=z.device)
+    else:
+        m, e = out
+    _check(lib().fpe_horner_eval(coeffs.data_ptr(), coeffs.shape[0] - 1, z.data_ptr(), n,
+                                 m.data_ptr(), e.data_ptr(), _stream(stream)))
+    return m, e
+
+
+def to_complex(m, e):
+    """m * 2**e as complex128 (overflows to inf where the value leaves the FP64 range)."""
+    torch = _torch()
+    ee = e.clamp(-3000, 3000).to(torch.float64)
+    sc = torch.pow(2.0, ee)
+    return torch.complex(m.real * sc, m.imag * sc)

@@ -1,0 +1,194 @@
+// Internal declarations of the FPE library: plan layout, workspace layout and
+// device helpers shared by the kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fpe.h"
+
+namespace fpe {
+
+constexpr int kWave = 64;                 // CDNA wavefront width
+constexpr int kBuckets = 1 << 16;         // lambda bins of the point sort
+constexpr int kHullLds = 2048;            // cover vertices staged in LDS by the plan kernel
+constexpr double kEta = 0x1p-20;          // widening of the window ends before ceil/floor
+constexpr int kFixLoBits = 44;            // fixed-point low word of the chunk accumulators
+constexpr int32_t kNegInfScale = INT32_MIN;
+
+// Device view of a preconditioned polynomial.  All pointers point into the
+// caller's precondition workspace.
+struct DevPlan {
+    const double2 *coef;      // a_k for k in G_p, 0 elsewhere; k = 0 .. dt
+    const int32_t *gprefix;   // gprefix[k] = #(G_p within [0, k)); k = 0 .. dt + 1
+    const double *hull_k;     // cover vertices: abscissae k_i (exact in double)
+    const double *hull_s;     // cover vertices: s(a_{k_i})
+    int32_t nh;               // number of vertices; 0 when P == 0
+    int32_t v, dt;            // first and last nonzero index
+    int32_t T;                // threshold offset p + s(dt - v) + 3
+    int32_t chunk;            // coefficient chunk length C of the window kernel
+    int32_t fix_shift;        // scale of the fixed-point chunk accumulators
+    int32_t coef_shift;       // coef holds a_k 2^-coef_shift (keeps window sums in range)
+    double2 a0;               // a_0, returned at z = 0
+};
+
+// Workspace of one evaluation of n points, carved from the caller's buffer.
+struct EvalWs {
+    int32_t *ell, *rr;            // window [l, r] per point (l > r: finished or empty)
+    long long *eref;              // reference exponent: every kept term is < 2^eref
+    uint32_t *key;                // lambda bin (kBuckets for finished points)
+    int32_t *perm;                // points sorted by bin
+    unsigned long long *acc;      // 4 per point: fixed-point (re hi, re lo, im hi, im lo)
+    int32_t *hist, *cursor;       // kBuckets + 1 each
+    int32_t *glo, *ghi, *gtiles;  // per group of kWave sorted points
+    int32_t *goff;                // exclusive scan of gtiles (n_groups + 1)
+    int2 *tiles;                  // (group, chunk) per tile
+    int32_t *ctl;                 // [0] tiles, [1] tile cursor, [2] valid points
+    int64_t n, n_groups, tile_cap;
+};
+
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base);
+
+// Read-only tables are read through the constant address space in device code:
+// a wave-uniform index then becomes a scalar load, one per wavefront, broadcast
+// to its 64 lanes.  (The host pass only parses kernel bodies.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FPE_CONST_AS __attribute__((address_space(4)))
+#else
+#define FPE_CONST_AS
+#endif
+typedef const FPE_CONST_AS double *const_table_t;
+
+// ---------------------------------------------------------------- device math
+// The error-free transforms below (TwoSum, TwoProd through fma) rely on every
+// product and sum being rounded separately: contracting a*b + c into one fma
+// would silently drop the low words.  Explicit fma() calls are unaffected.
+#define FPE_NO_CONTRACT _Pragma("clang fp contract(off)")
+
+struct dd2 { double hi, lo; };
+
+__host__ __device__ __forceinline__ dd2 two_sum(double a, double b) {
+    FPE_NO_CONTRACT
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__host__ __device__ __forceinline__ dd2 fast_two_sum(double a, double b) {
+    FPE_NO_CONTRACT
+    double s = a + b;
+    return {s, b - (s - a)};
+}
+
+// frexp-style exponent: x = f 2^k with |f| in [1/2, 1); x != 0 and finite
+__host__ __device__ __forceinline__ int exp_of(double x) { return ilogb(x) + 1; }
+
+// complex double-double with a separate binary exponent
+struct CDD { double rh, rl, ih, il; };
+
+__host__ __device__ __forceinline__ void cdd_renorm(CDD &x, long long &E) {
+    FPE_NO_CONTRACT
+    double m = fmax(fabs(x.rh), fabs(x.ih));
+    int k = exp_of(m);
+    x.rh = ldexp(x.rh, -k); x.rl = ldexp(x.rl, -k);
+    x.ih = ldexp(x.ih, -k); x.il = ldexp(x.il, -k);
+    E += k;
+}
+
+// x^2 for a complex double-double x
+__host__ __device__ __forceinline__ CDD cdd_sqr(const CDD &x) {
+    FPE_NO_CONTRACT
+    double p1 = x.rh * x.rh;
+    double e1 = fma(x.rh, x.rh, -p1);
+    e1 = fma(x.rh + x.rh, x.rl, e1);
+    double p2 = x.ih * x.ih;
+    double e2 = fma(x.ih, x.ih, -p2);
+    e2 = fma(x.ih + x.ih, x.il, e2);
+    dd2 s = two_sum(p1, -p2);
+    dd2 re = two_sum(s.hi, s.lo + (e1 - e2));
+    double q = x.rh * x.ih;
+    double eq = fma(x.rh, x.ih, -q);
+    eq = fma(x.rh, x.il, eq);
+    eq = fma(x.rl, x.ih, eq);
+    dd2 im = two_sum(q, eq);
+    return {re.hi, re.lo, 2.0 * im.hi, 2.0 * im.lo};
+}
+
+// x * w for a complex double-double x and a complex double w
+__host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, double wi) {
+    FPE_NO_CONTRACT
+    double p1 = x.rh * wr, e1 = fma(x.rh, wr, -p1);
+    e1 = fma(x.rl, wr, e1);
+    double p2 = x.ih * wi, e2 = fma(x.ih, wi, -p2);
+    e2 = fma(x.il, wi, e2);
+    dd2 s = two_sum(p1, -p2);
+    dd2 re = two_sum(s.hi, s.lo + (e1 - e2));
+    double p3 = x.rh * wi, e3 = fma(x.rh, wi, -p3);
+    e3 = fma(x.rl, wi, e3);
+    double p4 = x.ih * wr, e4 = fma(x.ih, wr, -p4);
+    e4 = fma(x.il, wr, e4);
+    dd2 t = two_sum(p3, p4);
+    dd2 im = two_sum(t.hi, t.lo + (e3 + e4));
+    return {re.hi, re.lo, im.hi, im.lo};
+}
+
+// w^n (n >= 0) for |Re w|, |Im w| < 1 with max in [1/2, 1): left-to-right binary
+// powering in double-double, renormalised after every product so that no
+// intermediate leaves the FP64 range.  Returns the rounded mantissa and adds the
+// binary exponent to E.  Relative error about (2 log2 n) 2^-100.
+__host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, double &pr, double &pi,
+                                        long long &E) {
+    if (n == 0) { pr = 1.0; pi = 0.0; return; }
+    CDD x = {wr, 0.0, wi, 0.0};
+    long long ex = 0;                 // x stands for (its mantissa) 2^ex
+    int top = 31 - __builtin_clz((unsigned)n);
+    for (int b = top - 1; b >= 0; --b) {
+        x = cdd_sqr(x);
+        ex *= 2;                      // squaring doubles the exponent
+        cdd_renorm(x, ex);
+        if ((n >> b) & 1) {
+            x = cdd_mul_d(x, wr, wi);
+            cdd_renorm(x, ex);
+        }
+    }
+    E += ex;
+    pr = x.rh + x.rl;
+    pi = x.ih + x.il;
+}
+
+// wave-wide reductions over the 64 lanes
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+}  // namespace fpe
+
+// Host-side plan handle (the ABI's opaque fpe_plan_s).
+struct fpe_plan_s {
+    fpe::DevPlan dev;
+    int64_t d, v, dt, nh, ngood, T, p, smax, smin_good;
+    std::vector<int64_t> hull_k, hull_s;
+    std::vector<uint8_t> good;       // d + 1 entries
+    int device;
+};
+
+namespace fpe {
+void set_error(const std::string &msg);
+fpe_status fail(fpe_status s, const std::string &msg);
+fpe_status hip_fail(hipError_t e, const char *what);
+}  // namespace fpe
+
+#define FPE_HIP_CHECK(call)                                                 \
+    do {                                                                    \
+        hipError_t _e = (call);                                             \
+        if (_e != hipSuccess) return ::fpe::hip_fail(_e, #call);            \
+    } while (0)

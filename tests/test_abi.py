@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every function include/fpe.h declares.
+
+Only host-side calls run here (size queries, argument validation, status
+strings): nothing that needs a GPU.
+"""
+import ctypes
+import os
+
+import pytest
+
+import paper_2211_06320_amd as fpe
+
+pytestmark = pytest.mark.skipif(not os.path.exists(fpe.LIB_PATH), reason="libfpe.so not built")
+
+
+def test_exports_every_declared_function():
+    names = fpe.header_functions()
+    assert {"fpe_precondition", "fpe_eval", "fpe_horner_eval", "fpe_eval_workspace_size"} <= set(names)
+    L = fpe.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    L = fpe.lib()
+    for code, name in fpe.STATUS.items():
+        assert L.fpe_status_string(code).decode() == name
+    assert L.fpe_status_string(99).decode() == "FPE_ERR_UNKNOWN"
+    assert L.fpe_abi_version() >= 1
+
+
+def test_workspace_size_queries_validate():
+    L = fpe.lib()
+    b = ctypes.c_size_t()
+    assert L.fpe_precondition_workspace_size(1000, 53, 0, ctypes.byref(b)) == fpe.FPE_OK
+    assert b.value >= 1001 * 16
+    small = b.value
+    assert L.fpe_precondition_workspace_size(10**6, 53, 0, ctypes.byref(b)) == fpe.FPE_OK
+    assert b.value > small
+    assert L.fpe_precondition_workspace_size(-1, 53, 0, ctypes.byref(b)) == 1
+    assert "degree" in L.fpe_last_error().decode()
+    assert L.fpe_precondition_workspace_size(10, 54, 0, ctypes.byref(b)) == 3
+    assert L.fpe_precondition_workspace_size(10, 0, 0, ctypes.byref(b)) == 3
+    assert L.fpe_precondition_workspace_size(10, 53, 7, ctypes.byref(b)) == 1
+    assert L.fpe_precondition_workspace_size(10, 53, 0, None) == 1
+
+
+def test_null_arguments_rejected_without_gpu_work():
+    L = fpe.lib()
+    h = ctypes.c_void_p()
+    assert L.fpe_precondition(None, 10, 53, 0, None, 0, None, ctypes.byref(h)) == 1
+    assert L.fpe_eval(None, None, 0, None, None, None, None, None, 0, None) == 1
+    assert L.fpe_horner_eval(None, -1, None, 0, None, None, None) == 1
+    assert L.fpe_plan_info(None, None) == 1
+    assert L.fpe_plan_destroy(None) == 0

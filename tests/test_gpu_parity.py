@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+Integer work (scales, cover, good set) must match bit for bit.  The window ends
+are integers decided in FP64 on both sides (lambda, the vertex values and the
+linear solve); they must agree, with a one-index difference tolerated only where
+a crossing lies within rounding of an integer.  Values must satisfy
+|FPE - reference| <= 2^-44 sum_k |a_k||z|^k, the reference being the oracle's
+compensated Horner of the full polynomial (or its double-double window sum at a
+wider precision, where the full Horner is too slow).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_06320_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 2.0 ** -44
+
+
+@pytest.fixture(scope="module")
+def fpe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2211_06320_amd as m
+    m.lib()
+    return m
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev())
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_eval(fpe, coeffs, z, p=53):
+    plan = fpe.precondition(to_dev(coeffs), p)
+    m, e, t, w = plan.eval(to_dev(z), terms=True, window=True)
+    torch.cuda.synchronize()
+    return plan, m.cpu().numpy(), e.cpu().numpy(), t.cpu().numpy(), w.cpu().numpy()
+
+
+def assert_plan_matches(plan, coeffs, p):
+    ref = oracle.precondition(coeffs, p)
+    ri = ref.info()
+    gi = plan.info()
+    assert (gi.d, gi.v, gi.dt, gi.n_hull, gi.n_good, gi.T, gi.p) == \
+        (ri.d, ri.v, ri.dt, ri.n_hull, ri.n_good, ri.T, ri.p)
+    hk, hs, good = plan.export()
+    rk, rs = ref.hull()
+    assert np.array_equal(hk, rk) and np.array_equal(hs, rs)
+    assert np.array_equal(good, ref.good())
+    return ref
+
+
+def assert_windows(w, ref, frac_exact=0.999):
+    dl = w[:, 0] - ref["l"]
+    dr = w[:, 1] - ref["r"]
+    assert np.abs(dl).max(initial=0) <= 1 and np.abs(dr).max(initial=0) <= 1
+    same = (dl == 0) & (dr == 0)
+    assert same.mean() >= frac_exact, same.mean()
+    return same
+
+
+def assert_values(m, e, coeffs, z, tol=TOL):
+    hm, he = oracle.horner(coeffs, z)
+    dm, de = oracle.absum(coeffs, z)
+    err = oracle.scaled_error(m, e, hm, he, dm, de)
+    finite = np.isfinite(z.real) & np.isfinite(z.imag)
+    worst = float(err[finite].max(initial=0.0))
+    assert worst <= tol, (worst, math.log2(max(worst, 1e-300)))
+    return worst
+
+
+def assert_normalised(m, e):
+    mx = np.maximum(np.abs(m.real), np.abs(m.imag))
+    ok = (mx == 0) | ((mx >= 0.5) & (mx < 1.0))
+    assert ok.all()
+    assert (e[mx == 0] == 0).all()
+
+
+# ----------------------------------------------------------------------------- plans
+def _plan_cases():
+    w = workloads
+    n = np.arange(101)
+    cases = {
+        "uniform_d1000": w.uniform_coeffs(1000, 1),
+        "wide_d4096": w.wide_coeffs(4096, 3),
+        "sparse_wide_d8192": w.sparse_wide_coeffs(8192, 3),
+        "halfcircle_d100": np.exp2(np.floor(np.sqrt((n + 1.0) * (101 - n)))).astype(complex),
+        "worked_example": np.array([2.0 ** x for x in [-3, 5, -4, 15, 13, -5, 26, 15, 29, 29, 17]], complex),
+        "zeros_at_ends": np.concatenate([[0, 0], w.uniform_coeffs(50, 9), [0, 0, 0]]),
+        "monomial": np.array([0, 0, 0, 2 - 1j], complex),
+        "constant": np.array([3 + 4j], complex),
+        "all_zero": np.zeros(7, complex),
+    }
+    return cases
+
+
+@pytest.mark.parametrize("name", list(_plan_cases()))
+@pytest.mark.parametrize("p", [53, 24, 6])
+def test_plan_bit_exact(fpe, name, p):
+    say(f"plan {name} p={p}")
+    c = _plan_cases()[name]
+    plan = fpe.precondition(to_dev(c), p)
+    torch.cuda.synchronize()
+    assert_plan_matches(plan, c, p)
+
+
+# ----------------------------------------------------------------------------- evaluation
+def test_small_uniform_all_points(fpe):
+    """d = 1000, 10^4 spherical points: windows, term counts and values at every point."""
+    wl = workloads.workload("uniform_d1000")
+    say("eval uniform_d1000 n=10000")
+    plan, m, e, t, w = gpu_eval(fpe, wl.coeffs, wl.points)
+    ref = assert_plan_matches(plan, wl.coeffs, 53).eval(wl.points)
+    same = assert_windows(w, ref)
+    assert np.array_equal(t[same], ref["terms"][same])
+    assert_normalised(m, e)
+    worst = assert_values(m, e, wl.coeffs, wl.points)
+    say(f"  max scaled error {worst:.3e}")
+    assert (t <= wl.degree + 1).all()
+
+
+def test_long_windows_several_chunks(fpe):
+    """Points near |z| = 1 have windows of thousands of terms: several C-term chunks."""
+    d = 20_000
+    c = workloads.uniform_coeffs(d, 21)
+    rng = np.random.default_rng(3)
+    r = 2.0 ** rng.uniform(-0.02, 0.02, 3000)
+    th = rng.uniform(0, 2 * np.pi, 3000)
+    z = np.concatenate([r * np.exp(1j * th), workloads.spherical_points(1000, 5)])
+    say(f"eval near-unit-circle d={d} n={len(z)}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    chunk = plan.info().chunk
+    assert ((w[:, 1] // chunk) - (w[:, 0] // chunk) >= 2).sum() > 1000
+    ref = oracle.precondition(c, 53).eval(z)
+    assert_windows(w, ref)
+    assert_normalised(m, e)
+    worst = assert_values(m, e, c, z)
+    say(f"  max scaled error {worst:.3e}")
+
+
+@pytest.mark.parametrize("kind", ["wide", "sparse_wide"])
+def test_wide_dynamic_range(fpe, kind):
+    """|a_k| = 2^g, g ~ N(0, 40^2), dense and 1 % sparse: a cover with many slopes."""
+    d = 1 << 16
+    c = workloads.wide_coeffs(d, 3) if kind == "wide" else workloads.sparse_wide_coeffs(d, 3)
+    z = workloads.spherical_points(4096, 13)
+    say(f"eval {kind} d={d} n={len(z)}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    ref = assert_plan_matches(plan, c, 53).eval(z)
+    same = assert_windows(w, ref)
+    assert np.array_equal(t[same], ref["terms"][same])
+    assert_normalised(m, e)
+    worst = assert_values(m, e, c, z)
+    say(f"  max scaled error {worst:.3e}")
+
+
+def test_worked_example_windows(fpe):
+    """The degree-10 example of Section 4.2 at p = 6, through the GPU plan and windows."""
+    c = np.array([2.0 ** x for x in [-3, 5, -4, 15, 13, -5, 26, 15, 29, 29, 17]], complex)
+    z = np.array([1.0, 0.125, -1.0, 1j * 0.125, 2.0, 0.5 + 0.5j], complex)
+    say("eval worked example p=6")
+    plan, m, e, t, w = gpu_eval(fpe, c, z, p=6)
+    ref = oracle.precondition(c, 6).eval(z)
+    assert np.array_equal(w[:, 0], ref["l"]) and np.array_equal(w[:, 1], ref["r"])
+    assert np.array_equal(t, ref["terms"])
+    # Q_0 and Q_{-3} of the paper are kept
+    good = plan.export()[2]
+    for i, want in ((0, {6, 8, 9}), (1, {1, 3, 6, 8, 9})):
+        kept = {k for k in range(w[i, 0], w[i, 1] + 1) if good[k]}
+        assert want <= kept
+
+
+def test_edge_cases(fpe):
+    say("eval edge cases")
+    # special points
+    c = np.array([3 + 4j, 1, -2j, 0.5], complex)
+    z = np.array([0, complex(np.inf, 0), complex(np.nan, 1), complex(1, -np.inf), 1e-300, 1e300, 0.5 - 0.25j], complex)
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    assert m[0] == (3 + 4j) / 8 and e[0] == 3 and t[0] == 1 and tuple(w[0]) == (0, 0)
+    assert np.isnan(m[1:4].real).all() and (t[1:4] == 0).all() and (w[1:4, 0] > w[1:4, 1]).all()
+    assert_values(m[4:], e[4:], c, z[4:])
+    # all-zero polynomial
+    plan, m, e, t, w = gpu_eval(fpe, np.zeros(9, complex), z[4:])
+    assert (m == 0).all() and (e == 0).all() and (t == 0).all()
+    # leading and trailing zeros, a_0 = 0 (P(0) = 0), a monomial, a constant
+    for cc in (np.concatenate([[0, 0], workloads.uniform_coeffs(30, 2), [0, 0]]),
+               np.array([0, 0, 0, 2 - 1j], complex), np.array([3 - 1j], complex),
+               np.array([1, 1], complex)):
+        zz = np.concatenate([[0], workloads.spherical_points(300, 7)])
+        plan, m, e, t, w = gpu_eval(fpe, cc, zz)
+        ref = oracle.precondition(cc, 53).eval(zz)
+        assert_windows(w, ref, 0.99)
+        assert_values(m, e, cc, zz)
+        assert_normalised(m, e)
+    # n = 0 is a no-op
+    plan = fpe.precondition(to_dev(c), 53)
+    mm, ee = plan.eval(torch.zeros(0, dtype=torch.complex128, device=dev()))
+    assert mm.numel() == 0
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
+def test_ragged_point_counts(fpe, n):
+    c = workloads.uniform_coeffs(3000, 4)
+    z = workloads.spherical_points(n, 100 + n)
+    say(f"eval ragged n={n}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    ref = oracle.precondition(c, 53).eval(z)
+    assert_windows(w, ref, 0.99)
+    assert_values(m, e, c, z)
+
+
+def test_deterministic(fpe):
+    """Each point's arithmetic does not depend on which points share its wavefront."""
+    wl = workloads.workload("uniform_d1000")
+    c = np.concatenate([wl.coeffs, workloads.uniform_coeffs(9000, 8)])
+    z = workloads.spherical_points(20_000, 44)
+    say("eval twice, bitwise")
+    plan = fpe.precondition(to_dev(c), 53)
+    zd = to_dev(z)
+    m1, e1 = plan.eval(zd)
+    m2, e2 = plan.eval(zd)
+    perm = torch.randperm(len(z), device=dev())
+    m3, e3 = plan.eval(zd[perm].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(m1, m2) and torch.equal(e1, e2)
+    inv = torch.argsort(perm)
+    assert torch.equal(m3[inv], m1) and torch.equal(e3[inv], e1)
+
+
+def test_horner_baseline(fpe):
+    wl = workloads.workload("uniform_d1000")
+    say("horner d=1000 n=10000")
+    m, e = fpe.horner_eval(to_dev(wl.coeffs), to_dev(wl.points))
+    torch.cuda.synchronize()
+    m, e = m.cpu().numpy(), e.cpu().numpy()
+    assert_normalised(m, e)
+    assert_values(m, e, wl.coeffs, wl.points)
+    z = np.array([0, 1e200, -3e160 + 1j, complex(np.nan, 0)], complex)
+    m, e = fpe.horner_eval(to_dev(wl.coeffs), to_dev(z))
+    torch.cuda.synchronize()
+    m, e = m.cpu().numpy(), e.cpu().numpy()
+    assert np.isnan(m[3].real)
+    assert_values(m[:3], e[:3], wl.coeffs, z[:3])
+
+
+# ----------------------------------------------------------------------------- full size
+def test_full_size_d1e6(fpe):
+    """d = 10^6, 10^6 spherical points, in the launch configuration the bench times.
+
+    Every point: normalised outputs, 1 <= terms <= d + 1.  Seeded sample of
+    points: windows and term counts against the oracle at p = 53, values against
+    its double-double window sum at p = 116 (truncation far below the tolerance)
+    and, on a smaller sample, against compensated Horner of the full polynomial.
+    """
+    wl = workloads.workload("uniform_d1e6")
+    say("eval uniform_d1e6 n=1e6")
+    plan, m, e, t, w = gpu_eval(fpe, wl.coeffs, wl.points)
+    assert_normalised(m, e)
+    assert (t >= 1).all() and (t <= wl.degree + 1).all()
+    rng = np.random.default_rng(2026)
+    idx = rng.choice(len(wl.points), 2000, replace=False)
+    # include the longest windows
+    idx = np.unique(np.concatenate([idx, np.argsort(w[:, 0] - w[:, 1])[:20]]))
+    zs = wl.points[idx]
+    say("  oracle p=53 windows on 2020 sampled points")
+    ref = oracle.precondition(wl.coeffs, 53).eval(zs)
+    same = assert_windows(w[idx], ref, 0.995)
+    assert np.array_equal(t[idx][same], ref["terms"][same])
+    say("  oracle p=116 values")
+    wide = oracle.precondition(wl.coeffs, 116).eval(zs)
+    err = oracle.scaled_error(m[idx], e[idx], wide["m"], wide["e"], wide["dwin_m"], wide["dwin_e"])
+    say(f"  max scaled error vs wide window {err.max():.3e}")
+    assert err.max() <= TOL
+    say("  compensated Horner on 48 points")
+    sub = idx[:48]
+    worst = assert_values(m[sub], e[sub], wl.coeffs, wl.points[sub])
+    say(f"  max scaled error vs compensated Horner {worst:.3e}")
