@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Headline measurement: FPE evaluation throughput on one MI355X.
+
+Workload: one complex polynomial of degree d = 10^6 with Re, Im of the
+coefficients i.i.d. uniform on [-1, 1], evaluated at 10^6 points uniform on the
+Riemann sphere (seeded, synthetic), FP64, p = 53.  A step is one fpe_eval call
+over all points (the whole evaluation phase: plan, sort, window sums, combine),
+with the plan and the points resident in HBM.  Preconditioning is timed
+separately, as the paper does.
+
+Besides the JSON fields the driver reads, the line carries:
+  roofline      the window kernel (the dominant kernel) against the FP64 vector
+                peak: algorithmic flops per launch / its average launch time
+                from HIP events recorded around it on its stream
+  cpu_baseline  the oracle (plain C, FP64 plan + double-double window sum) on a
+                bounded sample of the same points, on the host's cores
+  horner_gpu    the same-GPU Horner baseline over all points
+  max_scaled_err  max |FPE - reference| / sum|a_k||z|^k on a seeded sample,
+                the reference being the oracle's window sum at p = 116
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "evaluations/sec at d=1e6 (FPE vs GPU Horner), max rel err vs FP64 oracle"
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(terms, window) -> float:
+    """Per point: 8 flops per kept term (one complex multiply-add, Section 5.2)
+    plus 6 flops per complex multiplication of z^l by repeated squaring
+    (2 log2 l multiplications, Section 8.2)."""
+    import numpy as np
+    U = terms.astype(np.float64)
+    l = window[:, 0].astype(np.float64)
+    mults = np.where(l >= 2, np.ceil(2.0 * np.log2(np.maximum(l, 1.0))), 0.0)
+    return float(8.0 * U.sum() + 6.0 * mults.sum())
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform_d1e6")
+    ap.add_argument("--horner-steps", type=int, default=2)
+    ap.add_argument("--no-horner", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--check-sample", type=int, default=1000)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: this build evaluates on a single MI355X "
+              f"(--gpus {args.gpus}, WORLD_SIZE {world} requested); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2211_06320_amd as fpe
+    from paper_2211_06320_amd import workloads
+
+    dev = torch.device("cuda:0")
+    wl = workloads.workload(args.workload)
+    n, d = len(wl.points), wl.degree
+    log(f"workload {wl.name}: d={d}, n={n}")
+    coeffs = torch.from_numpy(wl.coeffs).to(dev)
+    z = torch.from_numpy(wl.points).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    plan = fpe.precondition(coeffs, wl.p_bits)
+    torch.cuda.synchronize()
+    pre_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    log(f"precondition {pre_ms:.1f} ms: {info}")
+
+    # one untimed pass for the algorithmic work counts
+    m, e, terms, window = plan.eval(z, terms=True, window=True)
+    torch.cuda.synchronize()
+    terms_np, window_np = terms.cpu().numpy(), window.cpu().numpy()
+    flops = algorithmic_flops(terms_np, window_np)
+    out = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+
+    for _ in range(args.warmup):
+        plan.eval(z, out=out)
+    torch.cuda.synchronize()
+    fpe.profile_read()
+    fpe.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.eval(z, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    fpe.profile_enable(False)
+    total_ms = ev0.elapsed_time(ev1)
+    win_ms, launches = fpe.profile_read()
+    ms_per_step = total_ms / args.steps
+    value = n / (ms_per_step * 1e-3)
+    win_avg_ms = win_ms / max(launches, 1)
+    achieved = flops / (win_avg_ms * 1e-3) / 1e12
+    log(f"eval {ms_per_step:.3f} ms/step ({value:.3e} evals/s); window kernel {win_avg_ms:.3f} ms, "
+        f"{achieved:.2f} TFLOP/s algorithmic")
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "d": d, "n_points": n, "p_bits": wl.p_bits,
+                   "coefficients": "Re, Im i.i.d. uniform[-1,1]", "points": "uniform on the Riemann sphere",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_window", "kernel_ms": win_avg_ms,
+                     "algorithmic_flops": flops, "kept_terms": int(terms_np.sum())},
+        "precondition_ms": pre_ms,
+        "mean_terms": float(terms_np.mean()),
+    }
+
+    # accuracy on a seeded sample, against the oracle's wide window sum
+    import oracle
+    mm, ee = out[0].cpu().numpy(), out[1].cpu().numpy()
+    rng = np.random.default_rng(12345)
+    idx = rng.choice(n, min(args.check_sample, n), replace=False)
+    ref = oracle.precondition(wl.coeffs, 116).eval(wl.points[idx])
+    err = oracle.scaled_error(mm[idx], ee[idx], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+    res["max_scaled_err"] = float(err.max())
+    res["check_sample"] = int(len(idx))
+    log(f"max scaled error on {len(idx)} points: {err.max():.3e}")
+
+    if not args.no_horner:
+        hout = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+        fpe.horner_eval(coeffs, z, out=hout)
+        torch.cuda.synchronize()
+        h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        h0.record()
+        for _ in range(args.horner_steps):
+            fpe.horner_eval(coeffs, z, out=hout)
+        h1.record()
+        torch.cuda.synchronize()
+        hms = h0.elapsed_time(h1) / args.horner_steps
+        hm, he = hout[0].cpu().numpy(), hout[1].cpu().numpy()
+        herr = oracle.scaled_error(hm[idx], he[idx], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+        res["horner_gpu"] = {"value": n / (hms * 1e-3), "unit": "evaluations/s", "ms_per_step": hms,
+                             "max_scaled_err": float(herr.max()), "speedup_fpe": (n / (ms_per_step * 1e-3)) / (n / (hms * 1e-3))}
+        log(f"horner {hms:.1f} ms/step, max scaled error {herr.max():.3e}")
+
+    if not args.no_cpu:
+        threads = oracle.default_threads()
+        zs = wl.points[:args.cpu_sample]
+        cplan = oracle.precondition(wl.coeffs, wl.p_bits)
+        t0 = time.perf_counter()
+        cplan.eval(zs, nthreads=threads)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(zs) / dt, "unit": "evaluations/s", "cores": threads, "kind": "oracle",
+                               "sample": f"first {len(zs)} of the {n} points of {wl.name}, p={wl.p_bits}: "
+                                         f"FP64 plan + double-double window sum, {threads} threads, {dt:.2f} s wall"}
+        log(f"cpu oracle {len(zs) / dt:.3e} evals/s on {threads} threads")
+
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -92,9 +92,10 @@ fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits, uint32_t f
  *
  * Errors: FPE_ERR_INVALID_ARG (NULL pointer, d out of range, misaligned
  * workspace), FPE_ERR_PRECISION, FPE_ERR_WORKSPACE, FPE_ERR_NONFINITE (a NaN or
- * infinite coefficient), FPE_ERR_UNSUPPORTED (the good coefficients span more
- * binary orders of magnitude than one FP64 window can hold: max s - min good s
- * > 1900), FPE_ERR_HIP.  An all-zero polynomial is accepted (P == 0). */
+ * infinite coefficient), FPE_ERR_UNSUPPORTED (the scales of the good
+ * coefficients span more binary orders of magnitude than an FP64 window sum can
+ * hold: max s - min good s > 2 (958 - T)), FPE_ERR_HIP.  An all-zero polynomial
+ * is accepted (P == 0). */
 fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_t p_bits, uint32_t flags,
                             void *workspace_dev, size_t workspace_bytes,
                             hipStream_t stream, fpe_plan_t *out_plan);
@@ -159,6 +160,21 @@ fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n,
  * workspace.  Errors: FPE_ERR_INVALID_ARG, FPE_ERR_HIP. */
 fpe_status fpe_horner_eval(const double *coef_dev, int64_t d, const double *z_dev, int64_t n,
                            double *m_dev, int64_t *e_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Instrumentation (for measurement only).                                   */
+/* ------------------------------------------------------------------------- */
+
+/* on != 0: every later fpe_eval records a HIP event pair around its window
+ * kernel (the dominant kernel of an evaluation) on the call's stream; on == 0
+ * stops recording.  Events come from a library-owned pool (hipEventCreate, no
+ * device memory); the pool is process-wide and not thread-safe. */
+fpe_status fpe_profile_enable(int32_t on);
+
+/* Waits for every recorded event pair, writes the summed elapsed time of the
+ * window kernels in milliseconds and the number of launches, then forgets them.
+ * Either pointer may be NULL. */
+fpe_status fpe_profile_read(double *window_ms_host, int64_t *launches_host);
 
 #ifdef __cplusplus
 }

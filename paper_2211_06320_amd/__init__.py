@@ -73,6 +73,10 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_horner_eval.restype = i32
     L.fpe_horner_eval.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+    L.fpe_profile_enable.restype = i32
+    L.fpe_profile_enable.argtypes = [i32]
+    L.fpe_profile_read.restype = i32
+    L.fpe_profile_read.argtypes = [P(ctypes.c_double), P(i64)]
     _LIB = L
     return L
 
@@ -220,6 +224,19 @@ def horner_eval(coeffs, z, out=None, stream=None):
     _check(lib().fpe_horner_eval(coeffs.data_ptr(), coeffs.shape[0] - 1, z.data_ptr(), n,
                                  m.data_ptr(), e.data_ptr(), _stream(stream)))
     return m, e
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every later window-kernel launch (measurement only)."""
+    _check(lib().fpe_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(summed window-kernel milliseconds, launches) since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().fpe_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def to_complex(m, e):

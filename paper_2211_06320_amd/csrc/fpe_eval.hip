@@ -26,6 +26,8 @@
 // on parallelisation); here the sort is what lets a wavefront read one
 // coefficient per step for all of its lanes.
 #include <climits>
+#include <utility>
+#include <vector>
 
 #include "fpe_internal.h"
 
@@ -335,6 +337,19 @@ __global__ __launch_bounds__(256) void k_finalize(DevPlan P, int n, double2 *__r
 
 int g_num_cu = 0;
 
+// instrumentation: event pairs around k_window
+struct ProfileState {
+    bool on = false;
+    std::vector<hipEvent_t> pool;     // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+ProfileState g_prof;
+
+hipError_t prof_event(hipEvent_t *ev) {
+    if (!g_prof.pool.empty()) { *ev = g_prof.pool.back(); g_prof.pool.pop_back(); return hipSuccess; }
+    return hipEventCreate(ev);
+}
+
 }  // namespace
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base) {
@@ -423,10 +438,45 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
         k_tiles<<<gb, 256, 0, stream>>>(P, W);
         const int64_t want = (W.tile_cap + 3) / 4;
         const unsigned wb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)g_num_cu * 8));
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (g_prof.on) {
+            FPE_HIP_CHECK(prof_event(&ev0));
+            FPE_HIP_CHECK(prof_event(&ev1));
+            FPE_HIP_CHECK(hipEventRecord(ev0, stream));
+        }
         k_window<<<wb, 256, 0, stream>>>(P, z, m, e, W);
+        if (g_prof.on) {
+            FPE_HIP_CHECK(hipEventRecord(ev1, stream));
+            g_prof.pending.emplace_back(ev0, ev1);
+        }
         k_finalize<<<pb, 256, 0, stream>>>(P, ni, m, e, W);
     }
     FPE_HIP_CHECK(hipGetLastError());
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_profile_enable(int32_t on) {
+    g_prof.on = on != 0;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_profile_read(double *window_ms, int64_t *launches) {
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &pr : g_prof.pending) {
+        FPE_HIP_CHECK(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        FPE_HIP_CHECK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+        ++cnt;
+        g_prof.pool.push_back(pr.first);
+        g_prof.pool.push_back(pr.second);
+    }
+    g_prof.pending.clear();
+    if (window_ms) *window_ms = tot;
+    if (launches) *launches = cnt;
     set_error("");
     return FPE_OK;
 }
