@@ -1,29 +1,39 @@
 // Evaluation phase (Algorithm A_p, second block; Section 5.2 of arXiv 2211.06320)
 // on gfx950.
 //
-// One evaluation is a chain of short kernels on one stream:
-//   k_clear      zero the bin histogram and the control words
+// One evaluation is a chain of short kernels on one stream, without
+// device-scope atomics on the data path:
+//
 //   k_plan       per point: lambda = log2|z| (eq. defLambda), k_lambda and
 //                N = max(Ehat + lambda Id) (eq. defN) by binary search over the
 //                cover vertices staged in LDS, the window [l, r] (eq. def:LRN) by
-//                two binary searches and a linear solve, the term count, and a
-//                lambda bin for the sort
-//   k_scan_bins  exclusive scan of the bin histogram (one workgroup)
-//   k_scatter    counting-sort scatter: points ordered by lambda bin
+//                two binary searches and a linear solve, the term count and a
+//                lambda bin; per sort block an LDS histogram of the bins, written
+//                as one column of the (bin x block) count table
+//   k_scan_seg   exclusive scan of the count table in bin-major order
+//   k_scatter    counting-sort scatter (LDS cursors): sorted records
+//                (point index, window, reference exponent, z) in lambda order
 //   k_groups     per group of 64 consecutive sorted points (one wavefront):
-//                the union of their windows and its number of C-term chunks
-//   k_scan_groups, k_tiles   the list of (group, chunk) tiles
-//   k_window     persistent: one wavefront per tile.  Its 64 lanes share the
-//                coefficient stream (wave-uniform index, scalar loads) and each
-//                runs Horner's rule over its own part of the chunk; lanes whose
+//                the union of their windows and the work of its C-term chunks
+//   k_scan_seg, k_part_groups, k_part_waves   an equal-work partition of the
+//                (group, chunk) tiles over the window kernel's wavefronts
+//   k_window     every wavefront runs its contiguous range of tiles.  The 64
+//                lanes of a tile share the coefficient stream (wave-uniform
+//                index, scalar loads prefetched one batch ahead) and each runs
+//                Horner's rule over its own part of the chunk; lanes whose
 //                window is shorter are masked only at the ragged ends.  Then
-//                z^lo by double-double binary powering with an exact exponent,
-//                and either the final value or an exact fixed-point partial.
-//   k_finalize   points whose window spans several chunks: fixed-point sum to
-//                (mantissa, exponent)
+//                z^lo by double-double binary powering with an exact exponent.
+//                A window inside one chunk is written out at once; the chunk
+//                partials of longer windows are summed exactly in fixed point,
+//                in registers while the wavefront stays on the group
+//   k_finalize   windows of groups split across wavefronts: the sum of the
+//                wavefronts' fixed-point partials, to (mantissa, exponent)
 //
-// The paper sorts points by |z| only as a suggestion (Section 1 and Section 8.1,
-// on parallelisation); here the sort is what lets a wavefront read one
+// Every chunk partial is computed the same way whichever wavefront runs it and
+// fixed-point sums are exact, so results do not depend on the partition or on
+// which points share a wavefront.  The paper only suggests ordering points by
+// |z| and evaluating points of similar size together (Section 1; Section 8.1
+// on parallelisation); here the order is what lets a wavefront read one
 // coefficient per step for all of its lanes.
 #include <climits>
 #include <utility>
@@ -37,14 +47,20 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// lambda bin: a monotone map of lambda onto [0, kBuckets), finest near 0 where
-// windows are longest (bin width about 3.8e-5 in lambda there, 1.5e-3 at
-// |lambda| = 5); |lambda| <= 1075 + 31 keeps asinh(8 lambda) below 9.8
-__device__ __forceinline__ uint32_t lambda_bin(double lam) {
-    double t = asinh(8.0 * lam) * (1.0 / 20.0) + 0.5;
-    int b = (int)(t * (double)kBuckets);
-    b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
-    return (uint32_t)b;
+constexpr int kBins = 4096;            // lambda bins; bin kBins holds finished points
+constexpr int kSortThreads = 256;
+constexpr int kPerThread = 8;
+constexpr int kSortPoints = kSortThreads * kPerThread;
+constexpr int kSeg = 4096;             // scan segment
+
+// lambda bin: a monotone map of lambda onto [0, kBins), finest near 0 where the
+// windows of a flat cover are longest and vary fastest (a sort by this key loses
+// less than 1 % of lane efficiency against an exact sort by lambda on the
+// uniform and wide-range workloads); |lambda| <= 1106 keeps asinh below 14.6
+__device__ __forceinline__ int lambda_bin(double lam) {
+    double t = asinh(1024.0 * lam) * (1.0 / 34.0) + 0.5;
+    int b = (int)(t * (double)kBins);
+    return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
 }
 
 __device__ __forceinline__ void normalise(double re, double im, long long E, double2 &m, long long &e) {
@@ -55,287 +71,547 @@ __device__ __forceinline__ void normalise(double re, double im, long long E, dou
     e = E + k;
 }
 
-__global__ void k_clear(EvalWs W) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= kBuckets) W.hist[i] = 0;
-    if (i < 64) W.ctl[i] = 0;
+// global exclusive prefix of the finished-points bin = number of points with a window
+__device__ __forceinline__ int valid_points(const EvalWs &W) {
+    const int64_t idx = (int64_t)kBins * W.n_sort_blocks;
+    return W.tscan[idx] + W.bin_off[idx / kSeg];
 }
 
-__global__ __launch_bounds__(256) void k_plan(DevPlan P, const double2 *__restrict__ z, int n,
-                                              double2 *__restrict__ m_out, long long *__restrict__ e_out,
-                                              int32_t *__restrict__ terms, long long *__restrict__ win,
-                                              EvalWs W) {
+__global__ __launch_bounds__(kSortThreads) void k_plan(DevPlan P, const double2 *__restrict__ z, int n,
+                                                       double2 *__restrict__ m_out, long long *__restrict__ e_out,
+                                                       int32_t *__restrict__ terms, long long *__restrict__ win,
+                                                       EvalWs W) {
+    __shared__ int32_t hist[kBins + 1];
     __shared__ double s_k[kHullLds];
     __shared__ double s_s[kHullLds];
+    const int t = threadIdx.x, b = blockIdx.x;
+    for (int i = t; i <= kBins; i += kSortThreads) hist[i] = 0;
+    if (b == 0 && t < 64) W.ctl[t] = 0;               // scan tickets and totals
     const bool in_lds = P.nh <= kHullLds;
     if (in_lds)
-        for (int i = threadIdx.x; i < P.nh; i += blockDim.x) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+        for (int i = t; i < P.nh; i += kSortThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
     __syncthreads();
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
     const double *hk = in_lds ? s_k : P.hull_k;
     const double *hs = in_lds ? s_s : P.hull_s;
+    const int nh = P.nh;
 
-    const double2 zz = z[j];
-    int32_t l = 1, r = 0, cnt = 0;
-    long long wl = 0, wr = -1, er = 0;
-    uint32_t key = kBuckets;
-    bool done = true;
-    double2 mo = make_double2(0.0, 0.0);
-    long long eo = 0;
-    if (!isfinite(zz.x) || !isfinite(zz.y)) {
-        mo = make_double2(__builtin_nan(""), __builtin_nan(""));
-    } else if (P.nh == 0) {
-        // P == 0
-    } else if (zz.x == 0.0 && zz.y == 0.0) {
-        wl = 0; wr = 0;                                   // P(0) = a_0
-        if (P.v == 0) { normalise(P.a0.x, P.a0.y, 0, mo, eo); cnt = 1; }
+    for (int it = 0; it < kPerThread; ++it) {
+        const int j = b * kSortPoints + it * kSortThreads + t;
+        if (j >= n) break;
+        const double2 zz = z[j];
+        int32_t l = 1, r = 0, cnt = 0;
+        long long wl = 0, wr = -1, er = 0;
+        int key = kBins;
+        bool done = true;
+        double2 mo = make_double2(0.0, 0.0);
+        long long eo = 0;
+        if (!isfinite(zz.x) || !isfinite(zz.y)) {
+            mo = make_double2(__builtin_nan(""), __builtin_nan(""));
+        } else if (nh == 0) {
+            // P == 0
+        } else if (zz.x == 0.0 && zz.y == 0.0) {
+            wl = 0; wr = 0;                               // P(0) = a_0
+            if (P.v == 0) { normalise(P.a0.x, P.a0.y, 0, mo, eo); cnt = 1; }
+        } else {
+            done = false;
+            const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
+            const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
+            const double lam = (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
+            // k_lambda: Ehat + lambda Id is concave, so its vertex values rise
+            // then fall; the leftmost maximiser is the first vertex whose next
+            // value is not larger
+            int lo = 0, hi = nh - 1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
+                if (dF <= 0.0) hi = mid; else lo = mid + 1;
+            }
+            const int is = lo;
+            const double N = fma(lam, hk[is], hs[is]);
+            const double L = N - (double)P.T;
+            // left end: the crossing of the level L on the rising branch [0, is]
+            double xL;
+            if (fma(lam, hk[0], hs[0]) >= L) {
+                xL = hk[0];
+            } else {
+                int a = 0, c = is;                          // F(a) < L <= F(c)
+                while (c - a > 1) {
+                    int mid = (a + c) >> 1;
+                    if (fma(lam, hk[mid], hs[mid]) < L) a = mid; else c = mid;
+                }
+                double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
+                xL = hk[a] + (L - Fa) * (hk[c] - hk[a]) / (Fc - Fa);
+            }
+            // right end: the crossing on the falling branch [is, nh - 1]
+            double xR;
+            if (fma(lam, hk[nh - 1], hs[nh - 1]) >= L) {
+                xR = hk[nh - 1];
+            } else {
+                int a = is, c = nh - 1;                     // F(a) >= L > F(c)
+                while (c - a > 1) {
+                    int mid = (a + c) >> 1;
+                    if (fma(lam, hk[mid], hs[mid]) >= L) a = mid; else c = mid;
+                }
+                double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
+                xR = hk[a] + (Fa - L) * (hk[c] - hk[a]) / (Fa - Fc);
+            }
+            l = (int32_t)fmax(ceil(xL - kEta), (double)P.v);
+            r = (int32_t)fmin(floor(xR + kEta), (double)P.dt);
+            wl = l; wr = r;
+            cnt = P.gprefix[r + 1] - P.gprefix[l];
+            er = (long long)floor(N) + 2;
+            key = lambda_bin(lam);
+        }
+        if (done) { m_out[j] = mo; e_out[j] = eo; }
+        if (terms) terms[j] = cnt;
+        if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
+        W.ell[j] = l;
+        W.rr[j] = r;
+        W.eref[j] = er;
+        W.key[j] = key;
+        atomicAdd(&hist[key], 1);                       // LDS
+    }
+    __syncthreads();
+    for (int i = t; i <= kBins; i += kSortThreads) W.table[(size_t)i * W.n_sort_blocks + b] = hist[i];
+}
+
+// Exclusive scan of int32 values in segments of kSeg = 4096 (1024 threads x 4,
+// coalesced 16-byte loads).  Every block scans its segment and writes the
+// segment-local exclusive prefix to out and the segment total to seg_sum; the
+// last block to finish (ticket) scans the totals into seg_off.  A global prefix
+// is out[i] + seg_off[i / kSeg].
+__device__ int32_t block_scan_seg(const int32_t *in, int32_t *out, int n, int32_t carry) {
+    __shared__ int32_t wsum[16];
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    int32_t v[4];
+    const int i0 = 4 * t;
+    if (i0 + 3 < n && ((reinterpret_cast<uintptr_t>(in) & 15) == 0)) {
+        int4 q = reinterpret_cast<const int4 *>(in)[t];
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
     } else {
-        done = false;
-        const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
-        const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
-        const double lam = (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
-        const int nh = P.nh;
-        // k_lambda: Ehat + lambda Id is concave, so its vertex values rise then
-        // fall; the leftmost maximiser is the first i whose next value is not larger
-        int lo = 0, hi = nh - 1;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
-            if (dF <= 0.0) hi = mid; else lo = mid + 1;
-        }
-        const int is = lo;
-        const double N = fma(lam, hk[is], hs[is]);
-        const double L = N - (double)P.T;
-        // left end: the crossing of the level L on the rising branch [0, is]
-        double xL;
-        if (fma(lam, hk[0], hs[0]) >= L) {
-            xL = hk[0];
-        } else {
-            int a = 0, b = is;                              // F(a) < L <= F(b)
-            while (b - a > 1) {
-                int mid = (a + b) >> 1;
-                if (fma(lam, hk[mid], hs[mid]) < L) a = mid; else b = mid;
-            }
-            double Fa = fma(lam, hk[a], hs[a]), Fb = fma(lam, hk[b], hs[b]);
-            xL = hk[a] + (L - Fa) * (hk[b] - hk[a]) / (Fb - Fa);
-        }
-        // right end: the crossing on the falling branch [is, nh - 1]
-        double xR;
-        if (fma(lam, hk[nh - 1], hs[nh - 1]) >= L) {
-            xR = hk[nh - 1];
-        } else {
-            int a = is, b = nh - 1;                         // F(a) >= L > F(b)
-            while (b - a > 1) {
-                int mid = (a + b) >> 1;
-                if (fma(lam, hk[mid], hs[mid]) >= L) a = mid; else b = mid;
-            }
-            double Fa = fma(lam, hk[a], hs[a]), Fb = fma(lam, hk[b], hs[b]);
-            xR = hk[a] + (Fa - L) * (hk[b] - hk[a]) / (Fa - Fb);
-        }
-        double cl = ceil(xL - kEta), cr = floor(xR + kEta);
-        l = (int32_t)fmax(cl, (double)P.v);
-        r = (int32_t)fmin(cr, (double)P.dt);
-        wl = l; wr = r;
-        cnt = P.gprefix[r + 1] - P.gprefix[l];
-        er = (long long)floor(N) + 2;
-        key = lambda_bin(lam);
-        if (l / P.chunk != r / P.chunk) {
-            unsigned long long *a = W.acc + 4 * (size_t)j;
-            a[0] = 0; a[1] = 0; a[2] = 0; a[3] = 0;
-        }
+        for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n) ? in[i0 + k] : 0;
     }
-    if (done) { m_out[j] = mo; e_out[j] = eo; }
-    if (terms) terms[j] = cnt;
-    if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
-    W.ell[j] = done ? 1 : l;
-    W.rr[j] = done ? 0 : r;
-    W.eref[j] = er;
-    W.key[j] = key;
-    atomicAdd(&W.hist[key], 1);
-}
-
-// exclusive scan of `count` ints in one workgroup of 1024 threads
-__device__ void block_exclusive_scan(const int32_t *in, int32_t *out, int count, int32_t *total) {
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x, T = blockDim.x;
-    const int per = (count + T - 1) / T;
-    const int b = t * per, e = min(count, b + per);
-    int32_t s = 0;
-    for (int i = b; i < e; ++i) s += in[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        int32_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    const int32_t s1 = v[0] + v[1], s2 = s1 + v[2], tot = s2 + v[3];
+    int32_t x = tot;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
     }
-    int32_t run = part[t] - s;   // exclusive prefix of this thread's segment
-    for (int i = b; i < e; ++i) { int32_t x = in[i]; out[i] = run; run += x; }
-    if (t == T - 1 && total) *total = part[t];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_bins(EvalWs W) {
-    __shared__ int32_t tot;
-    block_exclusive_scan(W.hist, W.cursor, kBuckets + 1, threadIdx.x == blockDim.x - 1 ? &tot : nullptr);
+    if (lane == kWave - 1) wsum[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) W.ctl[2] = W.cursor[kBuckets];   // points with a window
+    if (wave == 0) {
+        int32_t w = lane < 16 ? wsum[lane] : 0;
+        for (int o = 1; o < 16; o <<= 1) {
+            int32_t y = __shfl_up(w, o, kWave);
+            if (lane >= o) w += y;
+        }
+        if (lane < 16) wsum[lane] = w;
+    }
+    __syncthreads();
+    const int32_t excl = carry + (wave ? wsum[wave - 1] : 0) + x - tot;
+    const int32_t pre[4] = {excl, excl + v[0], excl + s1, excl + s2};
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) out[i0 + k] = pre[k];
+    const int32_t block_total = wsum[15];
+    __syncthreads();
+    return block_total;
 }
 
-__global__ __launch_bounds__(256) void k_scatter(EvalWs W, int n) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int pos = atomicAdd(&W.cursor[W.key[j]], 1);
-    W.perm[pos] = j;
+__global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                   int64_t count, int32_t *__restrict__ seg_sum,
+                                                   int32_t *__restrict__ seg_off, int32_t *__restrict__ ticket,
+                                                   int32_t *__restrict__ total) {
+    __shared__ int last;
+    const int b = blockIdx.x, nseg = gridDim.x;
+    const int64_t base = (int64_t)b * kSeg;
+    const int32_t tot = block_scan_seg(in + base, out + base, (int)min((int64_t)kSeg, count - base), 0);
+    if (threadIdx.x == 0) {
+        seg_sum[b] = tot;
+        __threadfence();
+        last = atomicAdd(ticket, 1) == nseg - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    int32_t carry = 0;
+    for (int s0 = 0; s0 < nseg; s0 += kSeg)
+        carry += block_scan_seg(seg_sum + s0, seg_off + s0, min(kSeg, nseg - s0), carry);
+    if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(256) void k_groups(DevPlan P, EvalWs W) {
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const double2 *__restrict__ z, int n, EvalWs W) {
+    __shared__ int32_t cur[kBins + 1];
+    const int t = threadIdx.x, b = blockIdx.x;
+    for (int i = t; i <= kBins; i += kSortThreads) {
+        const int64_t idx = (int64_t)i * W.n_sort_blocks + b;
+        cur[i] = W.tscan[idx] + W.bin_off[idx / kSeg];
+    }
+    __syncthreads();
+    for (int it = 0; it < kPerThread; ++it) {
+        const int j = b * kSortPoints + it * kSortThreads + t;
+        if (j >= n) break;
+        const int key = W.key[j];
+        if (key == kBins) continue;                     // finished points are not sorted
+        const int pos = atomicAdd(&cur[key], 1);        // LDS
+        W.sperm[pos] = j;
+        W.sl[pos] = W.ell[j];
+        W.sr[pos] = W.rr[j];
+        W.seref[pos] = W.eref[j];
+        W.sz[pos] = z[j];
+    }
+}
+
+// Work of a (group, chunk) tile in units of 16 Horner steps, plus a fixed
+// overhead for loading the lanes' records, z^lo and the write-back.
+constexpr int kCostUnit = 16;
+constexpr int kTileOverhead = 4;
+
+__device__ __forceinline__ int tile_cost(int glo, int ghi, int c, int C) {
+    const int len = min(ghi, c * C + C - 1) - max(glo, c * C) + 1;
+    return (len + kCostUnit - 1) / kCostUnit + kTileOverhead;
+}
+
+__global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
     const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     if (g >= W.n_groups) return;
-    const int nvalid = W.ctl[2];
+    const int nvalid = valid_points(W);
     const int idx = g * kWave + lane;
     int l = INT_MAX, r = INT_MIN;
-    if (idx < nvalid) { int j = W.perm[idx]; l = W.ell[j]; r = W.rr[j]; }
+    if (idx < nvalid) { l = W.sl[idx]; r = W.sr[idx]; }
     const int lo = wave_min(l), hi = wave_max(r);
     if (lane == 0) {
+        const int C = P.chunk;
         W.glo[g] = lo;
         W.ghi[g] = hi;
-        W.gtiles[g] = hi >= lo ? hi / P.chunk - lo / P.chunk + 1 : 0;
+        int cost = 0;
+        if (hi >= lo) {
+            const int clo = lo / C, chi = hi / C;
+            cost = tile_cost(lo, hi, clo, C);
+            if (chi > clo) cost += tile_cost(lo, hi, chi, C) + (chi - clo - 1) * (C / kCostUnit + kTileOverhead);
+        }
+        W.gcost[g] = cost;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_groups(EvalWs W) {
-    __shared__ int32_t tot;
-    block_exclusive_scan(W.gtiles, W.goff, (int)W.n_groups, threadIdx.x == blockDim.x - 1 ? &tot : nullptr);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        W.goff[W.n_groups] = tot;
-        W.ctl[0] = tot;     // tiles
-        W.ctl[1] = 0;       // tile cursor of k_window
-    }
+// Equal-work partition of the tiles over the window kernel's wavefronts.  The
+// tiles, in (group, chunk) order, cover consecutive intervals of a cost axis of
+// length `total`; wavefront w owns the tiles whose interval starts in
+// [s_w, s_{w+1}), s_w = ceil(w total / NW), so its work is total / NW up to one
+// tile, and the owner of a tile starting at a is floor(a NW / total).
+__device__ __forceinline__ long long group_start(const EvalWs &W, int g) {
+    return (long long)W.gcum[g] + W.gseg_off[g / kSeg];
 }
 
-__global__ __launch_bounds__(256) void k_tiles(DevPlan P, EvalWs W) {
-    const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
+// per group: the wavefronts owning its first and last tiles
+__global__ __launch_bounds__(256) void k_part_groups(DevPlan P, EvalWs W) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= W.n_groups) return;
-    const int cnt = W.gtiles[g], base = W.goff[g], c0 = W.glo[g] / P.chunk;
-    for (int i = lane; i < cnt; i += kWave) W.tiles[base + i] = make_int2(g, c0 + i);
+    const long long total = W.ctl[0];
+    const int cost = W.gcost[g];
+    if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
+    const int C = P.chunk, NW = (int)W.n_waves;
+    const int glo = W.glo[g], ghi = W.ghi[g];
+    const long long A = group_start(W, g), B = A + cost;
+    const int c_last = tile_cost(glo, ghi, ghi / C, C);
+    W.gwave[g] = make_int2((int)(A * NW / total), (int)((B - c_last) * NW / total));
 }
 
-// one Horner step acc <- acc z + a_K (4 FMAs); a_K read from the table cf
-#define HSTEP(K)                                              \
-    do {                                                      \
-        const double ar_ = cf[2 * (K)], ai_ = cf[2 * (K) + 1]; \
-        double nr_ = fma(hr, zr, fma(-hi_, zi, ar_));         \
-        double ni_ = fma(hr, zi, fma(hi_, zr, ai_));          \
-        hr = nr_; hi_ = ni_;                                  \
-    } while (0)
+// per wavefront: its first tile as (group, chunk), or (group, -1) for "the first
+// tile of the first group with tiles at or after this one"; (G, 0) past the end
+__global__ __launch_bounds__(256) void k_part_waves(DevPlan P, EvalWs W) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = P.chunk;
+    if (w > NW) return;
+    const long long total = W.ctl[0];
+    const long long sw = ((long long)w * total + NW - 1) / NW;
+    if (w == NW || total == 0 || sw >= total) { W.wstart[w] = make_int2(G, 0); return; }
+    // the last group starting at or before s_w
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (group_start(W, mid) <= sw) lo = mid; else hi = mid - 1;
+    }
+    const int g = lo;
+    const long long A = group_start(W, g), B = A + W.gcost[g];
+    if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
+    const int glo = W.glo[g], ghi = W.ghi[g];
+    const int clo = glo / C, chi = ghi / C;
+    const int c_first = tile_cost(glo, ghi, clo, C);
+    const int c_last = chi > clo ? tile_cost(glo, ghi, chi, C) : c_first;
+    const int c_mid = C / kCostUnit + kTileOverhead;
+    // the tile whose interval holds s_w, and its start
+    int c;
+    long long a;
+    if (sw < A + c_first || chi == clo) { c = clo; a = A; }
+    else if (sw >= B - c_last) { c = chi; a = B - c_last; }
+    else {
+        const long long q = (sw - A - c_first) / c_mid;
+        c = clo + 1 + (int)q;
+        a = A + c_first + q * c_mid;
+    }
+    int2 st;
+    if (a == sw) st = make_int2(g, c);
+    else if (c < chi) st = make_int2(g, c + 1);
+    else st = make_int2(g + 1, -1);
+    W.wstart[w] = st;
+}
 
-__global__ __launch_bounds__(256) void k_window(DevPlan P, const double2 *__restrict__ z,
-                                                double2 *__restrict__ m_out, long long *__restrict__ e_out,
-                                                EvalWs W) {
+// (g, c) with c < 0: the first tile of the first group at or after g with tiles
+__device__ __forceinline__ void resolve_tile(const EvalWs &W, int C, int &g, int &c) {
+    const int G = (int)W.n_groups;
+    if (c >= 0) return;
+    while (g < G && W.gcost[g] == 0) ++g;
+    c = g < G ? W.glo[g] / C : 0;
+}
+
+// One Horner step acc <- acc z + a, a = (ar, ai) wave-uniform:
+//   hr' = hr zr + (ar - hi zi),  hi' = hi zr + (ai + hr zi)
+// four VOP3 FMAs whose addends are read straight from scalar registers (written
+// out because the compiler otherwise copies half of them into vector registers).
+__device__ __forceinline__ void horner_step(double &hr, double &hi, double zr, double zi, double ar, double ai) {
+    double nr, ni;
+    asm("v_fma_f64 %0, -%3, %4, %5\n\t"
+        "v_fma_f64 %1, %2, %4, %6\n\t"
+        "v_fma_f64 %0, %2, %7, %0\n\t"
+        "v_fma_f64 %1, %3, %7, %1"
+        : "=&v"(nr), "=&v"(ni)
+        : "v"(hr), "v"(hi), "v"(zi), "s"(ar), "s"(ai), "v"(zr));
+    hr = nr;
+    hi = ni;
+}
+#define HSTEP2(AR, AI) horner_step(hr, hi_, zr, zi, (AR), (AI))
+#define HSTEP(K) HSTEP2(cf[2 * (K)], cf[2 * (K) + 1])
+
+constexpr int kBatch = 4;   // coefficients per scalar-load batch (64 bytes, one s_load_dwordx16)
+
+__device__ __forceinline__ void load_batch(double *dst, const_table_t p) {
+#pragma unroll
+    for (int q = 0; q < 2 * kBatch; ++q) dst[q] = p[q];
+}
+
+constexpr int kWindowThreads = 256;
+constexpr int kWindowWaves = kWindowThreads / kWave;
+
+// fixed-point form of a partial value (qr + i qi) 2^E relative to 2^eref: a
+// high word (integer part of value 2^(fix_shift - eref)) and a low word
+// (fix_lo more bits), summed exactly across chunks
+__device__ __forceinline__ void fix_add(const DevPlan &P, double qr, double qi, long long E, long long eref,
+                                        long long &a0, long long &a1, long long &a2, long long &a3) {
+    long long sh = E - eref + P.fix_shift;
+    sh = sh < -2200 ? -2200 : (sh > 200 ? 200 : sh);
+    const double xr = ldexp(qr, (int)sh), xi = ldexp(qi, (int)sh);
+    const double hr0 = trunc(xr), hi0 = trunc(xi);
+    a0 += (long long)hr0;
+    a1 += (long long)rint(ldexp(xr - hr0, P.fix_lo));
+    a2 += (long long)hi0;
+    a3 += (long long)rint(ldexp(xi - hi0, P.fix_lo));
+}
+
+__device__ __forceinline__ void fix_out(const DevPlan &P, long long a0, long long a1, long long a2, long long a3,
+                                        long long eref, double2 &m, long long &e) {
+    const int f = P.fix_shift;
+    const double vr = ldexp((double)a0, -f) + ldexp((double)a1, -f - P.fix_lo);
+    const double vi = ldexp((double)a2, -f) + ldexp((double)a3, -f - P.fix_lo);
+    normalise(vr, vi, eref, m, e);
+}
+
+__global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *__restrict__ m_out,
+                                                           long long *__restrict__ e_out, EvalWs W) {
     const int lane = threadIdx.x % kWave;
-    const int total = W.ctl[0];
-    const int nvalid = W.ctl[2];
+    const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
+    if (w >= W.n_waves) return;
+    const int nvalid = valid_points(W);
+    const int G = (int)W.n_groups;
     const int C = P.chunk;
     // the coefficient table is read-only for the whole evaluation: wave-uniform
     // indices into it become scalar loads
     const_table_t cf = (const_table_t)P.coef;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&W.ctl[1], 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, kWave));
-        if (t >= total) break;
-        const int2 gc = W.tiles[t];
-        const int g = __builtin_amdgcn_readfirstlane(gc.x);
-        const int c = __builtin_amdgcn_readfirstlane(gc.y);
+    int g, c, ge, ce;
+    {
+        const int2 st = W.wstart[w], en = W.wstart[w + 1];
+        g = __builtin_amdgcn_readfirstlane(st.x);
+        c = __builtin_amdgcn_readfirstlane(st.y);
+        ge = __builtin_amdgcn_readfirstlane(en.x);
+        ce = __builtin_amdgcn_readfirstlane(en.y);
+    }
+    resolve_tile(W, C, g, c);
+    resolve_tile(W, C, ge, ce);
+    // a wavefront may own no tile (a tile's work can exceed one share); the
+    // finalize kernel still reads its slots, so they start at zero
+    {
+        long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * 4;
+        long long *s1 = W.slots + ((size_t)(2 * w + 1) * kWave + lane) * 4;
+        s0[0] = 0; s0[1] = 0; s0[2] = 0; s0[3] = 0;
+        s1[0] = 0; s1[1] = 0; s1[2] = 0; s1[3] = 0;
+    }
+    bool first_segment = true;
+    // one pass per group segment: the consecutive tiles of one group this
+    // wavefront owns
+    while (g < G && !(g == ge && c == ce)) {
+        const int glo = __builtin_amdgcn_readfirstlane(W.glo[g]);
+        const int ghi = __builtin_amdgcn_readfirstlane(W.ghi[g]);
+        const int clo = glo / C, chi = ghi / C;
+        const int seg_c0 = c;
         const int idx = g * kWave + lane;
         const bool valid = idx < nvalid;
-        const int j = valid ? W.perm[idx] : 0;
-        const int l = valid ? W.ell[j] : 1, r = valid ? W.rr[j] : 0;
-        const int c0 = c * C, c1 = c0 + C - 1;
-        const int lo = max(l, c0), hi = min(r, c1);
-        const bool act = valid && lo <= hi;
-        const int Khi = __builtin_amdgcn_readfirstlane(wave_max(act ? hi : INT_MIN));
-        const int Klo = __builtin_amdgcn_readfirstlane(wave_min(act ? lo : INT_MAX));
-        const int Ahi = __builtin_amdgcn_readfirstlane(wave_min(act ? hi : INT_MAX));
-        const int Alo = __builtin_amdgcn_readfirstlane(wave_max(act ? lo : INT_MIN));
-        // the union of the lanes' windows may have a gap at this chunk
-        if (Khi < Klo) continue;
-        const double2 zz = act ? z[j] : make_double2(0.0, 0.0);
+        const int l = valid ? W.sl[idx] : 1, r = valid ? W.sr[idx] : 0;
+        const bool multi = valid && (l / C != r / C);
+        const double2 zz = valid ? W.sz[idx] : make_double2(0.0, 0.0);
+        const long long eref = multi ? W.seref[idx] : 0;
         const double zr = zz.x, zi = zz.y;
-        double hr = 0.0, hi_ = 0.0;
-        if (Ahi >= Alo) {
-            // ragged top: lanes start at their own hi
-            for (int k = Khi; k > Ahi; --k) { if (k <= hi) HSTEP(k); }
-            // common part: every active lane steps; wave-uniform coefficient
-            int k = Ahi;
-            for (; k - 3 >= Alo; k -= 4) {
-                HSTEP(k); HSTEP(k - 1); HSTEP(k - 2); HSTEP(k - 3);
+        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (;;) {
+            // ---- tile (g, c): this lane's part [lo, hi] of chunk c
+            const int c0 = c * C, c1 = c0 + C - 1;
+            const int lo = max(l, c0), hi = min(r, c1);
+            const bool act = valid && lo <= hi;
+            const int Khi = __builtin_amdgcn_readfirstlane(wave_max(act ? hi : INT_MIN));
+            const int Klo = __builtin_amdgcn_readfirstlane(wave_min(act ? lo : INT_MAX));
+            const int Ahi = __builtin_amdgcn_readfirstlane(wave_min(act ? hi : INT_MAX));
+            const int Alo = __builtin_amdgcn_readfirstlane(wave_max(act ? lo : INT_MIN));
+            if (Khi >= Klo) {
+                double hr = 0.0, hi_ = 0.0;
+                if (Ahi >= Alo) {
+                    // ragged top: lanes start at their own hi
+                    for (int k = Khi; k > Ahi; --k) { if (k <= hi) HSTEP(k); }
+                    // common part: every active lane steps.  Coefficients come in batches
+                    // of kBatch (one 64-byte scalar load each).  Scalar loads may return
+                    // out of order, so a wait for one batch waits for every batch in
+                    // flight: the next batch is requested right after the first step of
+                    // the current one (which waited for it), and arrives while the
+                    // remaining steps run.
+                    int k = Ahi;
+                    const int nb = (Ahi - Alo + 1) / kBatch;
+                    if (nb > 0) {
+                        const_table_t base = cf + 2 * (Ahi - kBatch + 1);   // batch b at base - 2 kBatch b
+                        double A[2 * kBatch], B[2 * kBatch];
+                        load_batch(A, base);
+                        int bi = 0;
+                        for (; bi + 2 <= nb; bi += 2) {
+                            HSTEP2(A[2 * kBatch - 2], A[2 * kBatch - 1]);
+                            __builtin_amdgcn_sched_barrier(0);
+                            load_batch(B, base - 2 * kBatch * (bi + 1));
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int s2 = kBatch - 2; s2 >= 0; --s2) HSTEP2(A[2 * s2], A[2 * s2 + 1]);
+                            HSTEP2(B[2 * kBatch - 2], B[2 * kBatch - 1]);
+                            __builtin_amdgcn_sched_barrier(0);
+                            if (bi + 2 < nb) load_batch(A, base - 2 * kBatch * (bi + 2));
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int s2 = kBatch - 2; s2 >= 0; --s2) HSTEP2(B[2 * s2], B[2 * s2 + 1]);
+                        }
+                        if (bi < nb) {
+#pragma unroll
+                            for (int s2 = kBatch - 1; s2 >= 0; --s2) HSTEP2(A[2 * s2], A[2 * s2 + 1]);
+                        }
+                        k -= kBatch * nb;
+                    }
+                    for (; k >= Alo; --k) HSTEP(k);
+                    // ragged bottom: lanes stop at their own lo
+                    for (int k2 = Alo - 1; k2 >= Klo; --k2) { if (k2 >= lo) HSTEP(k2); }
+                } else {
+                    for (int k = Khi; k >= Klo; --k) { if (k >= lo && k <= hi) HSTEP(k); }
+                }
+                if (act) {
+                    // multiply by z^lo: z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1)
+                    long long E = P.coef_shift;
+                    double pr = 1.0, pi = 0.0;
+                    if (lo > 0) {
+                        const int ez = exp_of(fmax(fabs(zr), fabs(zi)));
+                        cpow_dd(ldexp(zr, -ez), ldexp(zi, -ez), lo, pr, pi, E);
+                        E += (long long)lo * ez;
+                    }
+                    const double qr = fma(hr, pr, -hi_ * pi);
+                    const double qi = fma(hr, pi, hi_ * pr);
+                    if (!multi) {
+                        double2 m;
+                        long long e;
+                        normalise(qr, qi, E, m, e);
+                        const int j = W.sperm[idx];
+                        m_out[j] = m;
+                        e_out[j] = e;
+                    } else {
+                        fix_add(P, qr, qi, E, eref, a0, a1, a2, a3);
+                    }
+                }
             }
-            for (; k >= Alo; --k) HSTEP(k);
-            // ragged bottom: lanes stop at their own lo
-            for (int k2 = Alo - 1; k2 >= Klo; --k2) { if (k2 >= lo) HSTEP(k2); }
-        } else {
-            for (int k = Khi; k >= Klo; --k) { if (k >= lo && k <= hi) HSTEP(k); }
+            // ---- next tile of this segment, if this wavefront owns it
+            if (c == chi || (g == ge && c + 1 == ce)) break;
+            ++c;
         }
-        if (!act) continue;
-        // multiply by z^lo: z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1)
-        long long E = P.coef_shift;
-        double pr = 1.0, pi = 0.0;
-        if (lo > 0) {
-            const int ez = exp_of(fmax(fabs(zr), fabs(zi)));
-            cpow_dd(ldexp(zr, -ez), ldexp(zi, -ez), lo, pr, pi, E);
-            E += (long long)lo * ez;
+        // ---- end of the segment: a group done entirely here is written out, a
+        // part of a group leaves its fixed-point sums in this wavefront's slot
+        // (0: its first segment, 1: its last)
+        if (multi) {
+            if (seg_c0 == clo && c == chi) {
+                double2 m;
+                long long e;
+                fix_out(P, a0, a1, a2, a3, eref, m, e);
+                const int j = W.sperm[idx];
+                m_out[j] = m;
+                e_out[j] = e;
+            } else {
+                long long *slot = W.slots + ((size_t)(2 * w + (first_segment ? 0 : 1)) * kWave + lane) * 4;
+                slot[0] = a0; slot[1] = a1; slot[2] = a2; slot[3] = a3;
+            }
         }
-        const double qr = fma(hr, pr, -hi_ * pi);
-        const double qi = fma(hr, pi, hi_ * pr);
-        if (l / C == r / C) {
-            double2 m;
-            long long e;
-            normalise(qr, qi, E, m, e);
-            m_out[j] = m;
-            e_out[j] = e;
-        } else {
-            // exact fixed-point partial: value 2^-(eref) * 2^fix_shift, split in a
-            // high word (integer part) and a low word (kFixLoBits more bits)
-            long long sh = E - W.eref[j] + P.fix_shift;
-            sh = sh < -2200 ? -2200 : (sh > 200 ? 200 : sh);
-            const double xr = ldexp(qr, (int)sh), xi = ldexp(qi, (int)sh);
-            const double hr0 = trunc(xr), hi0 = trunc(xi);
-            const long long ihr = (long long)hr0, ihi = (long long)hi0;
-            const long long ilr = (long long)rint(ldexp(xr - hr0, kFixLoBits));
-            const long long ili = (long long)rint(ldexp(xi - hi0, kFixLoBits));
-            unsigned long long *a = W.acc + 4 * (size_t)j;
-            atomicAdd(a + 0, (unsigned long long)ihr);
-            atomicAdd(a + 1, (unsigned long long)ilr);
-            atomicAdd(a + 2, (unsigned long long)ihi);
-            atomicAdd(a + 3, (unsigned long long)ili);
-        }
+        first_segment = false;
+        if (c < chi) { ++c; }
+        else { ++g; c = -1; resolve_tile(W, C, g, c); }
     }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(DevPlan P, int n, double2 *__restrict__ m_out,
-                                                  long long *__restrict__ e_out, EvalWs W) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int l = W.ell[j], r = W.rr[j];
-    if (l > r || l / P.chunk == r / P.chunk) return;
-    const unsigned long long *a = W.acc + 4 * (size_t)j;
-    const int f = P.fix_shift;
-    const double vr = ldexp((double)(long long)a[0], -f) + ldexp((double)(long long)a[1], -f - kFixLoBits);
-    const double vi = ldexp((double)(long long)a[2], -f) + ldexp((double)(long long)a[3], -f - kFixLoBits);
+// Points whose window spans several chunks, in groups split across
+// wavefronts: the sum of the fixed-point partials the owning wavefronts left
+// in their slots.  One workgroup per group; its threads stride over the owning
+// wavefronts (integer sums: the order does not matter).  The first owner may
+// hold the group as its last segment (slot 1); every later owner holds it as
+// its first segment (slot 0).
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
+                                                            long long *__restrict__ e_out, EvalWs W) {
+    __shared__ long long part[kFinalThreads / kWave][kWave][4];
+    const int g = blockIdx.x;
+    const int2 gw = W.gwave[g];
+    if (gw.x == gw.y) return;                        // written by its only wavefront
+    const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave, nq = kFinalThreads / kWave;
+    int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
+    resolve_tile(W, P.chunk, fg, fc);
+    const int side0 = fg == g ? 0 : 1;
+    long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int w = gw.x + q; w <= gw.y; w += nq) {
+        const long long *slot = W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4;
+        a0 += slot[0]; a1 += slot[1]; a2 += slot[2]; a3 += slot[3];
+    }
+    part[q][lane][0] = a0; part[q][lane][1] = a1; part[q][lane][2] = a2; part[q][lane][3] = a3;
+    __syncthreads();
+    if (q != 0) return;
+    for (int k = 1; k < nq; ++k) {
+        a0 += part[k][lane][0]; a1 += part[k][lane][1]; a2 += part[k][lane][2]; a3 += part[k][lane][3];
+    }
+    const int p = g * kWave + lane;
+    if (p >= valid_points(W) || W.sl[p] / P.chunk == W.sr[p] / P.chunk) return;
     double2 m;
     long long e;
-    normalise(vr, vi, W.eref[j], m, e);
+    fix_out(P, a0, a1, a2, a3, W.seref[p], m, e);
+    const int j = W.sperm[p];
     m_out[j] = m;
     e_out[j] = e;
 }
 
 int g_num_cu = 0;
+int g_window_blocks_per_cu = 0;
+
+// wavefronts of the window kernel: as many as are resident at once on the
+// device (the partition hands each one an equal share, so none may wait for a
+// second round)
+int64_t window_waves() {
+    return (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (g_window_blocks_per_cu > 0 ? g_window_blocks_per_cu : 1) *
+           kWindowWaves;
+}
 
 // instrumentation: event pairs around k_window
 struct ProfileState {
@@ -350,6 +626,21 @@ hipError_t prof_event(hipEvent_t *ev) {
     return hipEventCreate(ev);
 }
 
+// compute units and resident window workgroups per compute unit (once per process)
+hipError_t device_setup() {
+    if (g_num_cu > 0) return hipSuccess;
+    int dev = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_window),
+                                                        kWindowThreads, 0);
+    if (e != hipSuccess) return e;
+    g_window_blocks_per_cu = nb > 0 ? nb : 1;
+    g_num_cu = ncu > 0 ? ncu : 256;
+    return hipSuccess;
+}
+
 }  // namespace
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base) {
@@ -357,27 +648,39 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
     const int64_t G = (n + kWave - 1) / kWave;
+    const int64_t NB = (n + kSortPoints - 1) / kSortPoints;
     int64_t chunks = 0;
     if (P.nh > 0) chunks = (int64_t)P.dt / P.chunk - (int64_t)P.v / P.chunk + 1;
-    const int64_t cap = G * chunks;
+    const int64_t tlen = (int64_t)(kBins + 1) * NB;
+    const int64_t nseg_t = (tlen + kSeg - 1) / kSeg, nseg_g = (G + kSeg - 1) / kSeg;
     EvalWs w;
     w.ell = (int32_t *)take(sizeof(int32_t) * n);
     w.rr = (int32_t *)take(sizeof(int32_t) * n);
     w.eref = (long long *)take(sizeof(long long) * n);
-    w.key = (uint32_t *)take(sizeof(uint32_t) * n);
-    w.perm = (int32_t *)take(sizeof(int32_t) * n);
-    w.acc = (unsigned long long *)take(sizeof(unsigned long long) * 4 * n);
-    w.hist = (int32_t *)take(sizeof(int32_t) * (kBuckets + 1));
-    w.cursor = (int32_t *)take(sizeof(int32_t) * (kBuckets + 1));
-    w.glo = (int32_t *)take(sizeof(int32_t) * G);
-    w.ghi = (int32_t *)take(sizeof(int32_t) * G);
-    w.gtiles = (int32_t *)take(sizeof(int32_t) * G);
-    w.goff = (int32_t *)take(sizeof(int32_t) * (G + 1));
-    w.tiles = (int2 *)take(sizeof(int2) * (cap > 0 ? cap : 1));
+    w.key = (int32_t *)take(sizeof(int32_t) * n);
+    w.sperm = (int32_t *)take(sizeof(int32_t) * n);
+    w.sl = (int32_t *)take(sizeof(int32_t) * n);
+    w.sr = (int32_t *)take(sizeof(int32_t) * n);
+    w.seref = (long long *)take(sizeof(long long) * n);
+    w.sz = (double2 *)take(sizeof(double2) * n);
+    w.table = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
+    w.tscan = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
+    w.bin_sum = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));
+    w.bin_off = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));
+    w.glo = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.ghi = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gcost = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gcum = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gseg_sum = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
+    w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
+    w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
+    w.n_waves = window_waves();
+    w.wstart = (int2 *)take(sizeof(int2) * (w.n_waves + 1));
+    w.slots = (long long *)take(sizeof(long long) * 4 * kWave * 2 * w.n_waves);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
     w.n_groups = G;
-    w.tile_cap = cap;
+    w.n_sort_blocks = NB;
     if (ws) *ws = w;
     return off;
 }
@@ -391,7 +694,9 @@ extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t
     if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
     const int64_t G = (n + kWave - 1) / kWave;
     int64_t chunks = plan->nh > 0 ? plan->dev.dt / plan->dev.chunk - plan->dev.v / plan->dev.chunk + 1 : 0;
-    if (G * chunks >= INT32_MAX) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    if (G * chunks * (plan->dev.chunk / kCostUnit + kTileOverhead) >= INT32_MAX)
+        return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    FPE_HIP_CHECK(device_setup());
     *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr);
     set_error("");
     return FPE_OK;
@@ -420,36 +725,34 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     long long *win = reinterpret_cast<long long *>(window_dev);
     const int ni = (int)n;
     const unsigned pb = (unsigned)((n + 255) / 256);
-    const unsigned gb = (unsigned)((W.n_groups + 3) / 4);
+    const unsigned sb = (unsigned)W.n_sort_blocks;
+    const unsigned gb = (unsigned)((W.n_groups + 15) / 16);
+    const int64_t tlen = (int64_t)(kBins + 1) * W.n_sort_blocks;
 
-    if (g_num_cu == 0) {
-        int dev = 0;
-        FPE_HIP_CHECK(hipGetDevice(&dev));
-        FPE_HIP_CHECK(hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev));
-        if (g_num_cu <= 0) g_num_cu = 256;
-    }
-    k_clear<<<(kBuckets + 1 + 255) / 256, 256, 0, stream>>>(W);
-    k_plan<<<pb, 256, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
+    FPE_HIP_CHECK(device_setup());
+    k_plan<<<sb, kSortThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
     if (P.nh > 0) {
-        k_scan_bins<<<1, 1024, 0, stream>>>(W);
-        k_scatter<<<pb, 256, 0, stream>>>(W, ni);
-        k_groups<<<gb, 256, 0, stream>>>(P, W);
-        k_scan_groups<<<1, 1024, 0, stream>>>(W);
-        k_tiles<<<gb, 256, 0, stream>>>(P, W);
-        const int64_t want = (W.tile_cap + 3) / 4;
-        const unsigned wb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)g_num_cu * 8));
+        k_scan_seg<<<(unsigned)((tlen + kSeg - 1) / kSeg), 1024, 0, stream>>>(W.table, W.tscan, tlen, W.bin_sum,
+                                                                             W.bin_off, W.ctl + 4, W.ctl + 5);
+        k_scatter<<<sb, kSortThreads, 0, stream>>>(z, ni, W);
+        k_groups<<<gb, 1024, 0, stream>>>(P, W);
+        k_scan_seg<<<(unsigned)((W.n_groups + kSeg - 1) / kSeg), 1024, 0, stream>>>(
+            W.gcost, W.gcum, W.n_groups, W.gseg_sum, W.gseg_off, W.ctl + 6, W.ctl + 0);
+        k_part_groups<<<(unsigned)((W.n_groups + 255) / 256), 256, 0, stream>>>(P, W);
+        k_part_waves<<<(unsigned)((W.n_waves + 1 + 255) / 256), 256, 0, stream>>>(P, W);
+        const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (g_prof.on) {
             FPE_HIP_CHECK(prof_event(&ev0));
             FPE_HIP_CHECK(prof_event(&ev1));
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
-        k_window<<<wb, 256, 0, stream>>>(P, z, m, e, W);
+        k_window<<<wb, kWindowThreads, 0, stream>>>(P, m, e, W);
         if (g_prof.on) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
-        k_finalize<<<pb, 256, 0, stream>>>(P, ni, m, e, W);
+        k_finalize<<<(unsigned)W.n_groups, kFinalThreads, 0, stream>>>(P, m, e, W);
     }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");

@@ -14,10 +14,8 @@
 namespace fpe {
 
 constexpr int kWave = 64;                 // CDNA wavefront width
-constexpr int kBuckets = 1 << 16;         // lambda bins of the point sort
-constexpr int kHullLds = 2048;            // cover vertices staged in LDS by the plan kernel
+constexpr int kHullLds = 512;             // cover vertices staged in LDS by the plan kernel
 constexpr double kEta = 0x1p-20;          // widening of the window ends before ceil/floor
-constexpr int kFixLoBits = 44;            // fixed-point low word of the chunk accumulators
 constexpr int32_t kNegInfScale = INT32_MIN;
 
 // Device view of a preconditioned polynomial.  All pointers point into the
@@ -31,24 +29,31 @@ struct DevPlan {
     int32_t v, dt;            // first and last nonzero index
     int32_t T;                // threshold offset p + s(dt - v) + 3
     int32_t chunk;            // coefficient chunk length C of the window kernel
-    int32_t fix_shift;        // scale of the fixed-point chunk accumulators
+    int32_t fix_shift;        // scale of the fixed-point chunk accumulators (high word)
+    int32_t fix_lo;           // extra bits of their low word
     int32_t coef_shift;       // coef holds a_k 2^-coef_shift (keeps window sums in range)
     double2 a0;               // a_0, returned at z = 0
 };
 
 // Workspace of one evaluation of n points, carved from the caller's buffer.
 struct EvalWs {
-    int32_t *ell, *rr;            // window [l, r] per point (l > r: finished or empty)
+    int32_t *ell, *rr;            // window [l, r] per point, input order (l > r: finished)
     long long *eref;              // reference exponent: every kept term is < 2^eref
-    uint32_t *key;                // lambda bin (kBuckets for finished points)
-    int32_t *perm;                // points sorted by bin
-    unsigned long long *acc;      // 4 per point: fixed-point (re hi, re lo, im hi, im lo)
-    int32_t *hist, *cursor;       // kBuckets + 1 each
-    int32_t *glo, *ghi, *gtiles;  // per group of kWave sorted points
-    int32_t *goff;                // exclusive scan of gtiles (n_groups + 1)
-    int2 *tiles;                  // (group, chunk) per tile
-    int32_t *ctl;                 // [0] tiles, [1] tile cursor, [2] valid points
-    int64_t n, n_groups, tile_cap;
+    int32_t *key;                 // lambda bin per point
+    int32_t *sperm;               // sorted records: input index,
+    int32_t *sl, *sr;             //   window,
+    long long *seref;             //   reference exponent,
+    double2 *sz;                  //   point
+    int32_t *table, *tscan;       // (bin x sort block) counts, bin-major, and their scan
+    int32_t *bin_sum, *bin_off;   // per 4096-entry segment of the table scan
+    int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
+    int32_t *gcost, *gcum;        //   work of its tiles and its segment-local exclusive scan,
+    int2 *gwave;                  //   first and last window wavefront owning its tiles
+    int32_t *gseg_sum, *gseg_off; // per 4096-entry segment of the group scan
+    int2 *wstart;                 // per window wavefront: first tile (group, chunk); n_waves + 1
+    long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
+    int32_t *ctl;                 // [0] total work, [4] [6] scan tickets, [5] sorted points
+    int64_t n, n_groups, n_sort_blocks, n_waves;
 };
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base);

@@ -246,8 +246,15 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     P.v = (int32_t)plan->v;
     P.dt = (int32_t)plan->dt;
     P.T = (int32_t)plan->T;
-    P.chunk = 1024;
-    P.fix_shift = (int32_t)(60 - bitlen(std::max<int64_t>(plan->dt - plan->v + 1, 1)));
+    P.chunk = 2048;
+    // fixed-point accumulators of windows spanning several chunks: the high
+    // word holds value 2^(fix_shift - eref), whose sum over a window is below
+    // W / 4 < 2^(bitlen(W) - 2); the low word holds fix_lo more bits of each
+    // partial and its sum over at most `chunks` partials stays below 2^62
+    const int64_t wmax = std::max<int64_t>(plan->dt - plan->v + 1, 1);
+    const int64_t chunks = std::max<int64_t>(plan->dt / P.chunk - plan->v / P.chunk + 1, 1);
+    P.fix_shift = (int32_t)(60 - bitlen(wmax));
+    P.fix_lo = (int32_t)std::min<int64_t>(44, 62 - bitlen(chunks));
     P.coef_shift = (int32_t)shift;
     P.a0 = a0;
     *out_plan = plan.release();
