@@ -261,14 +261,47 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const double2 *__restr
     }
 }
 
-// Work of a (group, chunk) tile in units of 16 Horner steps, plus a fixed
-// overhead for loading the lanes' records, z^lo and the write-back.
+// Work of the (group, chunk) tiles, in Horner steps, counted in units of
+// (16 << cost_shift) steps: a tile's steps, plus per tile an overhead for
+// z^lo (binary powering: about kPowSteps steps per bit of the exponent, taken
+// as the bit length of the group's last index) and the write-back, plus once
+// per group the loading of its lanes' records.  Measured on gfx950, a powering
+// bit costs about six Horner steps.  The middle chunks of a group all cost the
+// same, which lets the partition locate a tile in O(1).
 constexpr int kCostUnit = 16;
-constexpr int kTileOverhead = 4;
+constexpr int kPowSteps = 6;
+constexpr int kTileSteps = 32;
+constexpr int kGroupSteps = 32;
 
-__device__ __forceinline__ int tile_cost(int glo, int ghi, int c, int C) {
-    const int len = min(ghi, c * C + C - 1) - max(glo, c * C) + 1;
-    return (len + kCostUnit - 1) / kCostUnit + kTileOverhead;
+struct GroupCost {
+    int clo, chi;              // first and last chunk of the group's union window
+    int first, mid, last;      // cost of its first, middle and last tiles
+};
+
+__device__ __forceinline__ int cost_units(int steps, int shift) {
+    const int u = kCostUnit << shift;
+    return (steps + u - 1) / u;
+}
+
+__device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int C, int shift) {
+    GroupCost gc;
+    gc.clo = glo / C;
+    gc.chi = ghi / C;
+    const int bits = 32 - __clz(ghi > 0 ? ghi : 1);
+    const int ov = cost_units(kPowSteps * bits + kTileSteps, shift);
+    const int g0 = cost_units(kGroupSteps, shift);
+    gc.mid = cost_units(C, shift) + ov;
+    if (gc.chi == gc.clo) {
+        gc.first = gc.last = cost_units(ghi - glo + 1, shift) + ov + g0;
+    } else {
+        gc.first = cost_units(gc.clo * C + C - glo, shift) + ov + g0;
+        gc.last = cost_units(ghi - gc.chi * C + 1, shift) + ov;
+    }
+    return gc;
+}
+
+__device__ __forceinline__ int group_total(const GroupCost &gc) {
+    return gc.chi == gc.clo ? gc.first : gc.first + gc.last + (gc.chi - gc.clo - 1) * gc.mid;
 }
 
 __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
@@ -281,16 +314,9 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
     if (idx < nvalid) { l = W.sl[idx]; r = W.sr[idx]; }
     const int lo = wave_min(l), hi = wave_max(r);
     if (lane == 0) {
-        const int C = P.chunk;
         W.glo[g] = lo;
         W.ghi[g] = hi;
-        int cost = 0;
-        if (hi >= lo) {
-            const int clo = lo / C, chi = hi / C;
-            cost = tile_cost(lo, hi, clo, C);
-            if (chi > clo) cost += tile_cost(lo, hi, chi, C) + (chi - clo - 1) * (C / kCostUnit + kTileOverhead);
-        }
-        W.gcost[g] = cost;
+        W.gcost[g] = hi >= lo ? group_total(group_cost(lo, hi, P.chunk, W.cost_shift)) : 0;
     }
 }
 
@@ -310,11 +336,10 @@ __global__ __launch_bounds__(256) void k_part_groups(DevPlan P, EvalWs W) {
     const long long total = W.ctl[0];
     const int cost = W.gcost[g];
     if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
-    const int C = P.chunk, NW = (int)W.n_waves;
-    const int glo = W.glo[g], ghi = W.ghi[g];
+    const int NW = (int)W.n_waves;
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], P.chunk, W.cost_shift);
     const long long A = group_start(W, g), B = A + cost;
-    const int c_last = tile_cost(glo, ghi, ghi / C, C);
-    W.gwave[g] = make_int2((int)(A * NW / total), (int)((B - c_last) * NW / total));
+    W.gwave[g] = make_int2((int)(A * NW / total), (int)((B - gc.last) * NW / total));
 }
 
 // per wavefront: its first tile as (group, chunk), or (group, -1) for "the first
@@ -335,24 +360,20 @@ __global__ __launch_bounds__(256) void k_part_waves(DevPlan P, EvalWs W) {
     const int g = lo;
     const long long A = group_start(W, g), B = A + W.gcost[g];
     if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
-    const int glo = W.glo[g], ghi = W.ghi[g];
-    const int clo = glo / C, chi = ghi / C;
-    const int c_first = tile_cost(glo, ghi, clo, C);
-    const int c_last = chi > clo ? tile_cost(glo, ghi, chi, C) : c_first;
-    const int c_mid = C / kCostUnit + kTileOverhead;
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], C, W.cost_shift);
     // the tile whose interval holds s_w, and its start
     int c;
     long long a;
-    if (sw < A + c_first || chi == clo) { c = clo; a = A; }
-    else if (sw >= B - c_last) { c = chi; a = B - c_last; }
+    if (sw < A + gc.first || gc.chi == gc.clo) { c = gc.clo; a = A; }
+    else if (sw >= B - gc.last) { c = gc.chi; a = B - gc.last; }
     else {
-        const long long q = (sw - A - c_first) / c_mid;
-        c = clo + 1 + (int)q;
-        a = A + c_first + q * c_mid;
+        const long long q = (sw - A - gc.first) / gc.mid;
+        c = gc.clo + 1 + (int)q;
+        a = A + gc.first + q * gc.mid;
     }
     int2 st;
     if (a == sw) st = make_int2(g, c);
-    else if (c < chi) st = make_int2(g, c + 1);
+    else if (c < gc.chi) st = make_int2(g, c + 1);
     else st = make_int2(g + 1, -1);
     W.wstart[w] = st;
 }
@@ -367,27 +388,90 @@ __device__ __forceinline__ void resolve_tile(const EvalWs &W, int C, int &g, int
 
 // One Horner step acc <- acc z + a, a = (ar, ai) wave-uniform:
 //   hr' = hr zr + (ar - hi zi),  hi' = hi zr + (ai + hr zi)
-// four VOP3 FMAs whose addends are read straight from scalar registers (written
-// out because the compiler otherwise copies half of them into vector registers).
+// four VOP3 FMAs whose addends are read straight from scalar registers, updating
+// the accumulator in place (written out because the compiler otherwise copies
+// half of the addends into vector registers, and the accumulator between
+// masked steps).
 __device__ __forceinline__ void horner_step(double &hr, double &hi, double zr, double zi, double ar, double ai) {
-    double nr, ni;
-    asm("v_fma_f64 %0, -%3, %4, %5\n\t"
-        "v_fma_f64 %1, %2, %4, %6\n\t"
-        "v_fma_f64 %0, %2, %7, %0\n\t"
-        "v_fma_f64 %1, %3, %7, %1"
-        : "=&v"(nr), "=&v"(ni)
-        : "v"(hr), "v"(hi), "v"(zi), "s"(ar), "s"(ai), "v"(zr));
-    hr = nr;
-    hi = ni;
+    double tr, ti;
+    asm volatile("v_fma_f64 %2, -%1, %4, %6\n\t"
+                 "v_fma_f64 %3, %0, %4, %7\n\t"
+                 "v_fma_f64 %0, %0, %5, %2\n\t"
+                 "v_fma_f64 %1, %1, %5, %3"
+                 : "+v"(hr), "+v"(hi), "=&v"(tr), "=&v"(ti)
+                 : "v"(zi), "v"(zr), "s"(ar), "s"(ai));
 }
-#define HSTEP2(AR, AI) horner_step(hr, hi_, zr, zi, (AR), (AI))
-#define HSTEP(K) HSTEP2(cf[2 * (K)], cf[2 * (K) + 1])
 
 constexpr int kBatch = 4;   // coefficients per scalar-load batch (64 bytes, one s_load_dwordx16)
 
 __device__ __forceinline__ void load_batch(double *dst, const_table_t p) {
 #pragma unroll
     for (int q = 0; q < 2 * kBatch; ++q) dst[q] = p[q];
+}
+
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima)
+__device__ __forceinline__ void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Which lanes take the step of coefficient k in a tile where lane i covers
+// [lo_i, hi_i]: all of them (the common part), those that have started
+// (k <= hi_i, the ragged top), those that have not finished (k >= lo_i, the
+// ragged bottom), or both tests.
+enum StepMask { kAll = 0, kTop = 1, kBottom = 2, kBoth = 3 };
+
+template <int M>
+__device__ __forceinline__ void masked_step(double &hr, double &hi_, double zr, double zi, double ar, double ai,
+                                            int k, int lo, int hi) {
+    if ((M & kTop) && k > hi) return;
+    if ((M & kBottom) && k < lo) return;
+    horner_step(hr, hi_, zr, zi, ar, ai);
+}
+
+template <int M>
+__device__ __forceinline__ void batch_steps(double &hr, double &hi_, double zr, double zi, const double *X, int kbase,
+                                            int lo, int hi) {
+#pragma unroll
+    for (int s2 = kBatch - 1; s2 >= 0; --s2) masked_step<M>(hr, hi_, zr, zi, X[2 * s2], X[2 * s2 + 1], kbase + s2, lo, hi);
+}
+
+// Horner steps for k = kfrom, kfrom - 1, ..., kto (none if kfrom < kto); kfrom
+// and kto are wave-uniform.  Coefficients come in batches of kBatch (one 64-byte
+// scalar load each), one batch ahead.  Scalar loads may return out of order, so
+// a wait for one batch waits for every batch in flight: each batch starts with
+// an unconditional wait for itself (nothing else is in flight then), requests
+// the next batch, and runs its steps, which need no further wait even when
+// they are masked.
+template <int M>
+__device__ __forceinline__ void run_steps(double &hr, double &hi_, double zr, double zi, const_table_t cf,
+                                          int kfrom, int kto, int lo, int hi) {
+    if (kfrom < kto) return;
+    const int nb = (kfrom - kto + 1) / kBatch;
+    int k = kfrom;
+    if (nb > 0) {
+        // batch b holds a_{kb}, ..., a_{kb + kBatch - 1}, kb = kfrom - kBatch (b + 1) + 1
+        const_table_t base = cf + 2 * (kfrom - kBatch + 1);
+        const int kb0 = kfrom - kBatch + 1;
+        double A[2 * kBatch], B[2 * kBatch];
+        load_batch(A, base);
+        int bi = 0;
+        for (; bi + 2 <= nb; bi += 2) {
+            wait_scalar_loads();
+            __builtin_amdgcn_sched_barrier(0);
+            load_batch(B, base - 2 * kBatch * (bi + 1));
+            __builtin_amdgcn_sched_barrier(0);
+            batch_steps<M>(hr, hi_, zr, zi, A, kb0 - kBatch * bi, lo, hi);
+            wait_scalar_loads();
+            __builtin_amdgcn_sched_barrier(0);
+            if (bi + 2 < nb) load_batch(A, base - 2 * kBatch * (bi + 2));
+            __builtin_amdgcn_sched_barrier(0);
+            batch_steps<M>(hr, hi_, zr, zi, B, kb0 - kBatch * (bi + 1), lo, hi);
+        }
+        if (bi < nb) {
+            wait_scalar_loads();
+            batch_steps<M>(hr, hi_, zr, zi, A, kb0 - kBatch * bi, lo, hi);
+        }
+        k -= kBatch * nb;
+    }
+    for (; k >= kto; --k) masked_step<M>(hr, hi_, zr, zi, cf[2 * k], cf[2 * k + 1], k, lo, hi);
 }
 
 constexpr int kWindowThreads = 256;
@@ -473,46 +557,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
             if (Khi >= Klo) {
                 double hr = 0.0, hi_ = 0.0;
                 if (Ahi >= Alo) {
-                    // ragged top: lanes start at their own hi
-                    for (int k = Khi; k > Ahi; --k) { if (k <= hi) HSTEP(k); }
-                    // common part: every active lane steps.  Coefficients come in batches
-                    // of kBatch (one 64-byte scalar load each).  Scalar loads may return
-                    // out of order, so a wait for one batch waits for every batch in
-                    // flight: the next batch is requested right after the first step of
-                    // the current one (which waited for it), and arrives while the
-                    // remaining steps run.
-                    int k = Ahi;
-                    const int nb = (Ahi - Alo + 1) / kBatch;
-                    if (nb > 0) {
-                        const_table_t base = cf + 2 * (Ahi - kBatch + 1);   // batch b at base - 2 kBatch b
-                        double A[2 * kBatch], B[2 * kBatch];
-                        load_batch(A, base);
-                        int bi = 0;
-                        for (; bi + 2 <= nb; bi += 2) {
-                            HSTEP2(A[2 * kBatch - 2], A[2 * kBatch - 1]);
-                            __builtin_amdgcn_sched_barrier(0);
-                            load_batch(B, base - 2 * kBatch * (bi + 1));
-                            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                            for (int s2 = kBatch - 2; s2 >= 0; --s2) HSTEP2(A[2 * s2], A[2 * s2 + 1]);
-                            HSTEP2(B[2 * kBatch - 2], B[2 * kBatch - 1]);
-                            __builtin_amdgcn_sched_barrier(0);
-                            if (bi + 2 < nb) load_batch(A, base - 2 * kBatch * (bi + 2));
-                            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                            for (int s2 = kBatch - 2; s2 >= 0; --s2) HSTEP2(B[2 * s2], B[2 * s2 + 1]);
-                        }
-                        if (bi < nb) {
-#pragma unroll
-                            for (int s2 = kBatch - 1; s2 >= 0; --s2) HSTEP2(A[2 * s2], A[2 * s2 + 1]);
-                        }
-                        k -= kBatch * nb;
-                    }
-                    for (; k >= Alo; --k) HSTEP(k);
-                    // ragged bottom: lanes stop at their own lo
-                    for (int k2 = Alo - 1; k2 >= Klo; --k2) { if (k2 >= lo) HSTEP(k2); }
+                    run_steps<kTop>(hr, hi_, zr, zi, cf, Khi, Ahi + 1, lo, hi);
+                    run_steps<kAll>(hr, hi_, zr, zi, cf, Ahi, Alo, lo, hi);
+                    run_steps<kBottom>(hr, hi_, zr, zi, cf, Alo - 1, Klo, lo, hi);
                 } else {
-                    for (int k = Khi; k >= Klo; --k) { if (k >= lo && k <= hi) HSTEP(k); }
+                    run_steps<kBoth>(hr, hi_, zr, zi, cf, Khi, Klo, lo, hi);
                 }
                 if (act) {
                     // multiply by z^lo: z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1)
@@ -643,14 +692,27 @@ hipError_t device_setup() {
 
 }  // namespace
 
+// Smallest cost unit shift for which the total tile work of n points fits the
+// int32 scans: at most G groups x (chunks x (C / u + powering overhead) + the
+// per-group part), u = 16 << shift; -1 if none does.
+int cost_shift_for(const DevPlan &P, int64_t n) {
+    const int64_t G = (n + kWave - 1) / kWave;
+    const int64_t chunks = P.nh > 0 ? (int64_t)P.dt / P.chunk - (int64_t)P.v / P.chunk + 1 : 0;
+    for (int sh = 0; sh <= 20; ++sh) {
+        const int64_t u = (int64_t)kCostUnit << sh;
+        auto units = [u](int64_t steps) { return (steps + u - 1) / u; };
+        const int64_t bound = G * (chunks * (units(P.chunk) + units(kPowSteps * 31 + kTileSteps)) + units(kGroupSteps));
+        if (bound < INT32_MAX) return sh;
+    }
+    return -1;
+}
+
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
     const int64_t G = (n + kWave - 1) / kWave;
     const int64_t NB = (n + kSortPoints - 1) / kSortPoints;
-    int64_t chunks = 0;
-    if (P.nh > 0) chunks = (int64_t)P.dt / P.chunk - (int64_t)P.v / P.chunk + 1;
     const int64_t tlen = (int64_t)(kBins + 1) * NB;
     const int64_t nseg_t = (tlen + kSeg - 1) / kSeg, nseg_g = (G + kSeg - 1) / kSeg;
     EvalWs w;
@@ -679,6 +741,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     w.slots = (long long *)take(sizeof(long long) * 4 * kWave * 2 * w.n_waves);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
+    w.cost_shift = cost_shift_for(P, n);
     w.n_groups = G;
     w.n_sort_blocks = NB;
     if (ws) *ws = w;
@@ -692,10 +755,7 @@ using namespace fpe;
 extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t *bytes) {
     if (!plan || !bytes) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
-    const int64_t G = (n + kWave - 1) / kWave;
-    int64_t chunks = plan->nh > 0 ? plan->dev.dt / plan->dev.chunk - plan->dev.v / plan->dev.chunk + 1 : 0;
-    if (G * chunks * (plan->dev.chunk / kCostUnit + kTileOverhead) >= INT32_MAX)
-        return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    if (cost_shift_for(plan->dev, n) < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
     FPE_HIP_CHECK(device_setup());
     *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr);
     set_error("");

@@ -16,6 +16,7 @@ namespace fpe {
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kHullLds = 512;             // cover vertices staged in LDS by the plan kernel
 constexpr double kEta = 0x1p-20;          // widening of the window ends before ceil/floor
+constexpr int kChunk = 512;               // coefficient chunk length C of the window kernel
 constexpr int32_t kNegInfScale = INT32_MIN;
 
 // Device view of a preconditioned polynomial.  All pointers point into the
@@ -54,6 +55,7 @@ struct EvalWs {
     long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
     int32_t *ctl;                 // [0] total work, [4] [6] scan tickets, [5] sorted points
     int64_t n, n_groups, n_sort_blocks, n_waves;
+    int32_t cost_shift;           // tile work is counted in units of (16 << cost_shift) steps
 };
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base);

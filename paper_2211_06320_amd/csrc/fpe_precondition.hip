@@ -246,7 +246,7 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     P.v = (int32_t)plan->v;
     P.dt = (int32_t)plan->dt;
     P.T = (int32_t)plan->T;
-    P.chunk = 2048;
+    P.chunk = kChunk;
     // fixed-point accumulators of windows spanning several chunks: the high
     // word holds value 2^(fix_shift - eref), whose sum over a window is below
     // W / 4 < 2^(bitlen(W) - 2); the low word holds fix_lo more bits of each
