@@ -4,19 +4,21 @@
 // One evaluation is a chain of short kernels on one stream, without
 // device-scope atomics on the data path:
 //
-//   k_plan       per point: lambda = log2|z| (eq. defLambda), k_lambda and
-//                N = max(Ehat + lambda Id) (eq. defN) by binary search over the
-//                cover vertices staged in LDS, the window [l, r] (eq. def:LRN) by
-//                two binary searches and a linear solve, the term count and a
-//                lambda bin; per sort block an LDS histogram of the bins, written
-//                as one column of the (bin x block) count table
+//   k_bounds     per point (one thread each): lambda = log2|z| (eq. defLambda),
+//                k_lambda and N = max(Ehat + lambda Id) (eq. defN) by binary
+//                search over the cover vertices staged in LDS, the window [l, r]
+//                (eq. def:LRN) by two binary searches and a linear solve, the
+//                term count, a reference exponent and a lambda bin; written as
+//                one 32-byte record per point
+//   k_hist       per sort block of 8192 points: an LDS histogram of the bins,
+//                written as one column of the (bin x block) count table
 //   k_scan_seg   exclusive scan of the count table in bin-major order
-//   k_scatter    counting-sort scatter (LDS cursors): sorted records
-//                (point index, window, reference exponent, z) in lambda order
+//   k_scatter    counting-sort scatter of the records (LDS cursors) into
+//                lambda-bin order
 //   k_groups     per group of 64 consecutive sorted points (one wavefront):
 //                the union of their windows and the work of its C-term chunks
-//   k_scan_seg, k_part_groups, k_part_waves   an equal-work partition of the
-//                (group, chunk) tiles over the window kernel's wavefronts
+//   k_scan_seg, k_partition   an equal-work partition of the (group, chunk)
+//                tiles over the window kernel's wavefronts
 //   k_window     every wavefront runs its contiguous range of tiles.  The 64
 //                lanes of a tile share the coefficient stream (wave-uniform
 //                index, scalar loads prefetched one batch ahead) and each runs
@@ -48,7 +50,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kBins = 4096;            // lambda bins; bin kBins holds finished points
-constexpr int kSortThreads = 256;
+constexpr int kBoundsThreads = 1024;   // window kernel-independent per-point work: one point per thread
+constexpr int kSortThreads = 1024;     // histogram and scatter: kPerThread points per thread
 constexpr int kPerThread = 8;
 constexpr int kSortPoints = kSortThreads * kPerThread;
 constexpr int kSeg = 4096;             // scan segment
@@ -77,100 +80,121 @@ __device__ __forceinline__ int valid_points(const EvalWs &W) {
     return W.tscan[idx] + W.bin_off[idx / kSeg];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_plan(DevPlan P, const double2 *__restrict__ z, int n,
-                                                       double2 *__restrict__ m_out, long long *__restrict__ e_out,
-                                                       int32_t *__restrict__ terms, long long *__restrict__ win,
-                                                       EvalWs W) {
-    __shared__ int32_t hist[kBins + 1];
+// Per point: lambda = log2|z| (eq. defLambda), k_lambda and N = max(Ehat +
+// lambda Id) (eq. defN) by binary search over the cover vertices, the window
+// [l, r] (eq. def:LRN) by two binary searches and a linear solve, the reference
+// exponent and the lambda bin.  Points with no window (z = 0, a non-finite z,
+// P == 0) get their value here and the bin kBins.
+__global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const double2 *__restrict__ z, int n,
+                                                           double2 *__restrict__ m_out,
+                                                           long long *__restrict__ e_out,
+                                                           int32_t *__restrict__ terms,
+                                                           long long *__restrict__ win, EvalWs W) {
     __shared__ double s_k[kHullLds];
     __shared__ double s_s[kHullLds];
-    const int t = threadIdx.x, b = blockIdx.x;
-    for (int i = t; i <= kBins; i += kSortThreads) hist[i] = 0;
-    if (b == 0 && t < 64) W.ctl[t] = 0;               // scan tickets and totals
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t < 64) W.ctl[t] = 0;      // scan tickets and totals
     const bool in_lds = P.nh <= kHullLds;
     if (in_lds)
-        for (int i = t; i < P.nh; i += kSortThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+        for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
     __syncthreads();
+    const int j = blockIdx.x * kBoundsThreads + t;
+    if (j >= n) return;
     const double *hk = in_lds ? s_k : P.hull_k;
     const double *hs = in_lds ? s_s : P.hull_s;
     const int nh = P.nh;
+    const double2 zz = z[j];
+    int32_t l = 1, r = 0, cnt = 0;                     // l > r: no window for the window kernel
+    long long wl = 0, wr = -1, er = 0;                 // reported window
+    int key = kBins;
+    bool done = true;
+    double2 mo = make_double2(0.0, 0.0);
+    long long eo = 0;
+    if (!isfinite(zz.x) || !isfinite(zz.y)) {
+        mo = make_double2(__builtin_nan(""), __builtin_nan(""));
+    } else if (nh == 0) {
+        // P == 0
+    } else if (zz.x == 0.0 && zz.y == 0.0) {
+        wl = 0; wr = 0;                                // P(0) = a_0
+        if (P.v == 0) { normalise(P.a0.x, P.a0.y, 0, mo, eo); cnt = 1; }
+    } else {
+        done = false;
+        const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
+        const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
+        const double lam = (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
+        // k_lambda: Ehat + lambda Id is concave, so its vertex values rise
+        // then fall; the leftmost maximiser is the first vertex whose next
+        // value is not larger
+        int lo = 0, hi = nh - 1;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
+            if (dF <= 0.0) hi = mid; else lo = mid + 1;
+        }
+        const int is = lo;
+        const double N = fma(lam, hk[is], hs[is]);
+        const double L = N - (double)P.T;
+        // left end: the crossing of the level L on the rising branch [0, is]
+        double xL;
+        if (fma(lam, hk[0], hs[0]) >= L) {
+            xL = hk[0];
+        } else {
+            int a = 0, c = is;                          // F(a) < L <= F(c)
+            while (c - a > 1) {
+                int mid = (a + c) >> 1;
+                if (fma(lam, hk[mid], hs[mid]) < L) a = mid; else c = mid;
+            }
+            double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
+            xL = hk[a] + (L - Fa) * (hk[c] - hk[a]) / (Fc - Fa);
+        }
+        // right end: the crossing on the falling branch [is, nh - 1]
+        double xR;
+        if (fma(lam, hk[nh - 1], hs[nh - 1]) >= L) {
+            xR = hk[nh - 1];
+        } else {
+            int a = is, c = nh - 1;                     // F(a) >= L > F(c)
+            while (c - a > 1) {
+                int mid = (a + c) >> 1;
+                if (fma(lam, hk[mid], hs[mid]) >= L) a = mid; else c = mid;
+            }
+            double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
+            xR = hk[a] + (Fa - L) * (hk[c] - hk[a]) / (Fa - Fc);
+        }
+        l = (int32_t)fmax(ceil(xL - kEta), (double)P.v);
+        r = (int32_t)fmin(floor(xR + kEta), (double)P.dt);
+        wl = l; wr = r;
+        if (terms) cnt = P.gprefix[r + 1] - P.gprefix[l];
+        er = (long long)floor(N) + 2;
+        key = lambda_bin(lam);
+    }
+    if (done) { m_out[j] = mo; e_out[j] = eo; }
+    if (terms) terms[j] = cnt;
+    if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
+    PointRec rc;
+    rc.z = zz;
+    rc.l = l;
+    rc.r = r;
+    rc.eref = er;
+    W.rec[j] = rc;
+    W.key[j] = key;
+}
 
+// Per sort block of kSortPoints consecutive points: the histogram of their
+// bins, written as one column of the (bin x block) count table.
+__global__ __launch_bounds__(kSortThreads) void k_hist(int n, EvalWs W) {
+    __shared__ int32_t hist[kBins + 1];
+    const int t = threadIdx.x, b = blockIdx.x;
+    for (int i = t; i <= kBins; i += kSortThreads) hist[i] = 0;
+    __syncthreads();
+    int keys[kPerThread];
+#pragma unroll
     for (int it = 0; it < kPerThread; ++it) {
         const int j = b * kSortPoints + it * kSortThreads + t;
-        if (j >= n) break;
-        const double2 zz = z[j];
-        int32_t l = 1, r = 0, cnt = 0;
-        long long wl = 0, wr = -1, er = 0;
-        int key = kBins;
-        bool done = true;
-        double2 mo = make_double2(0.0, 0.0);
-        long long eo = 0;
-        if (!isfinite(zz.x) || !isfinite(zz.y)) {
-            mo = make_double2(__builtin_nan(""), __builtin_nan(""));
-        } else if (nh == 0) {
-            // P == 0
-        } else if (zz.x == 0.0 && zz.y == 0.0) {
-            wl = 0; wr = 0;                               // P(0) = a_0
-            if (P.v == 0) { normalise(P.a0.x, P.a0.y, 0, mo, eo); cnt = 1; }
-        } else {
-            done = false;
-            const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
-            const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
-            const double lam = (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
-            // k_lambda: Ehat + lambda Id is concave, so its vertex values rise
-            // then fall; the leftmost maximiser is the first vertex whose next
-            // value is not larger
-            int lo = 0, hi = nh - 1;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
-                if (dF <= 0.0) hi = mid; else lo = mid + 1;
-            }
-            const int is = lo;
-            const double N = fma(lam, hk[is], hs[is]);
-            const double L = N - (double)P.T;
-            // left end: the crossing of the level L on the rising branch [0, is]
-            double xL;
-            if (fma(lam, hk[0], hs[0]) >= L) {
-                xL = hk[0];
-            } else {
-                int a = 0, c = is;                          // F(a) < L <= F(c)
-                while (c - a > 1) {
-                    int mid = (a + c) >> 1;
-                    if (fma(lam, hk[mid], hs[mid]) < L) a = mid; else c = mid;
-                }
-                double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
-                xL = hk[a] + (L - Fa) * (hk[c] - hk[a]) / (Fc - Fa);
-            }
-            // right end: the crossing on the falling branch [is, nh - 1]
-            double xR;
-            if (fma(lam, hk[nh - 1], hs[nh - 1]) >= L) {
-                xR = hk[nh - 1];
-            } else {
-                int a = is, c = nh - 1;                     // F(a) >= L > F(c)
-                while (c - a > 1) {
-                    int mid = (a + c) >> 1;
-                    if (fma(lam, hk[mid], hs[mid]) >= L) a = mid; else c = mid;
-                }
-                double Fa = fma(lam, hk[a], hs[a]), Fc = fma(lam, hk[c], hs[c]);
-                xR = hk[a] + (Fa - L) * (hk[c] - hk[a]) / (Fa - Fc);
-            }
-            l = (int32_t)fmax(ceil(xL - kEta), (double)P.v);
-            r = (int32_t)fmin(floor(xR + kEta), (double)P.dt);
-            wl = l; wr = r;
-            cnt = P.gprefix[r + 1] - P.gprefix[l];
-            er = (long long)floor(N) + 2;
-            key = lambda_bin(lam);
-        }
-        if (done) { m_out[j] = mo; e_out[j] = eo; }
-        if (terms) terms[j] = cnt;
-        if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
-        W.ell[j] = l;
-        W.rr[j] = r;
-        W.eref[j] = er;
-        W.key[j] = key;
-        atomicAdd(&hist[key], 1);                       // LDS
+        keys[it] = j < n ? W.key[j] : -1;
     }
+#pragma unroll
+    for (int it = 0; it < kPerThread; ++it)
+        if (keys[it] >= 0) atomicAdd(&hist[keys[it]], 1);     // LDS
     __syncthreads();
     for (int i = t; i <= kBins; i += kSortThreads) W.table[(size_t)i * W.n_sort_blocks + b] = hist[i];
 }
@@ -239,43 +263,53 @@ __global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ i
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_scatter(const double2 *__restrict__ z, int n, EvalWs W) {
+// Counting-sort scatter of the point records: bin-major positions from the
+// table scan, handed out within a block through LDS cursors.  Points of a bin
+// that share a block land in an unspecified order; results do not depend on it.
+__global__ __launch_bounds__(kSortThreads) void k_scatter(int n, EvalWs W) {
     __shared__ int32_t cur[kBins + 1];
     const int t = threadIdx.x, b = blockIdx.x;
     for (int i = t; i <= kBins; i += kSortThreads) {
         const int64_t idx = (int64_t)i * W.n_sort_blocks + b;
         cur[i] = W.tscan[idx] + W.bin_off[idx / kSeg];
     }
-    __syncthreads();
+    int keys[kPerThread];
+#pragma unroll
     for (int it = 0; it < kPerThread; ++it) {
         const int j = b * kSortPoints + it * kSortThreads + t;
-        if (j >= n) break;
-        const int key = W.key[j];
-        if (key == kBins) continue;                     // finished points are not sorted
-        const int pos = atomicAdd(&cur[key], 1);        // LDS
+        keys[it] = j < n ? W.key[j] : kBins;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kPerThread; ++it) {
+        if (keys[it] == kBins) continue;               // finished points are not sorted
+        const int j = b * kSortPoints + it * kSortThreads + t;
+        const PointRec rc = W.rec[j];
+        const int pos = atomicAdd(&cur[keys[it]], 1);  // LDS
+        W.srec[pos] = rc;
         W.sperm[pos] = j;
-        W.sl[pos] = W.ell[j];
-        W.sr[pos] = W.rr[j];
-        W.seref[pos] = W.eref[j];
-        W.sz[pos] = z[j];
     }
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
-// (16 << cost_shift) steps: a tile's steps, plus per tile an overhead for
-// z^lo (binary powering: about kPowSteps steps per bit of the exponent, taken
-// as the bit length of the group's last index) and the write-back, plus once
-// per group the loading of its lanes' records.  Measured on gfx950, a powering
-// bit costs about six Horner steps.  The middle chunks of a group all cost the
-// same, which lets the partition locate a tile in O(1).
+// (16 << cost_shift) steps.  A tile costs its steps plus a fixed part, plus the
+// binary powerings it runs, at about kPowSteps steps per bit of the exponent
+// (measured on gfx950): a full powering where some window of the group starts
+// in the chunk (at most the chunks up to the group's largest window start),
+// and an anchor every kAnchor chunks for the lanes that continue.  A group also
+// costs a fixed part once (records, w^C).  Middle tiles cost one of two
+// amounts, before and after the last window start, which lets the partition
+// locate a tile in O(1).
 constexpr int kCostUnit = 16;
-constexpr int kPowSteps = 6;
-constexpr int kTileSteps = 32;
-constexpr int kGroupSteps = 32;
+constexpr int kPowSteps = 10;
+constexpr int kTileSteps = 8;
+constexpr int kGroupSteps = 64;
 
 struct GroupCost {
     int clo, chi;              // first and last chunk of the group's union window
-    int first, mid, last;      // cost of its first, middle and last tiles
+    int first, last;           // cost of its first and last tiles (first: the whole group if clo == chi)
+    int ns, cs;                // the next ns middle tiles (a window may start there) cost cs each,
+    int cn;                    //   the other middle tiles cn each
 };
 
 __device__ __forceinline__ int cost_units(int steps, int shift) {
@@ -283,25 +317,34 @@ __device__ __forceinline__ int cost_units(int steps, int shift) {
     return (steps + u - 1) / u;
 }
 
-__device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int C, int shift) {
+__device__ __forceinline__ int bit_length(int x) { return x > 0 ? 32 - __clz(x) : 0; }
+
+// glo, ghi: the group's union window; gml: its largest window start
+__device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C, int shift) {
     GroupCost gc;
     gc.clo = glo / C;
     gc.chi = ghi / C;
-    const int bits = 32 - __clz(ghi > 0 ? ghi : 1);
-    const int ov = cost_units(kPowSteps * bits + kTileSteps, shift);
-    const int g0 = cost_units(kGroupSteps, shift);
-    gc.mid = cost_units(C, shift) + ov;
+    const int cl = gml / C;
+    const int pow_start = kPowSteps * bit_length(gml);
+    const int pow_cont = kPowSteps * bit_length(ghi) / kAnchor;
     if (gc.chi == gc.clo) {
-        gc.first = gc.last = cost_units(ghi - glo + 1, shift) + ov + g0;
-    } else {
-        gc.first = cost_units(gc.clo * C + C - glo, shift) + ov + g0;
-        gc.last = cost_units(ghi - gc.chi * C + 1, shift) + ov;
+        gc.first = gc.last = cost_units(ghi - glo + 1 + kTileSteps + kGroupSteps + pow_start, shift);
+        gc.ns = 0;
+        gc.cs = gc.cn = 1;
+        return gc;
     }
+    gc.first = cost_units(gc.clo * C + C - glo + kTileSteps + kGroupSteps + pow_start, shift);
+    gc.last = cost_units(ghi - gc.chi * C + 1 + kTileSteps + (gc.chi <= cl ? pow_start : 0) + pow_cont, shift);
+    gc.ns = max(0, min(cl, gc.chi - 1) - gc.clo);
+    gc.cs = cost_units(C + kTileSteps + pow_start + pow_cont, shift);
+    gc.cn = cost_units(C + kTileSteps + pow_cont, shift);
     return gc;
 }
 
-__device__ __forceinline__ int group_total(const GroupCost &gc) {
-    return gc.chi == gc.clo ? gc.first : gc.first + gc.last + (gc.chi - gc.clo - 1) * gc.mid;
+__device__ __forceinline__ long long group_total(const GroupCost &gc) {
+    if (gc.chi == gc.clo) return gc.first;
+    const long long nn = gc.chi - gc.clo - 1 - gc.ns;
+    return (long long)gc.first + gc.last + (long long)gc.ns * gc.cs + nn * gc.cn;
 }
 
 __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
@@ -311,12 +354,13 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
     const int nvalid = valid_points(W);
     const int idx = g * kWave + lane;
     int l = INT_MAX, r = INT_MIN;
-    if (idx < nvalid) { l = W.sl[idx]; r = W.sr[idx]; }
-    const int lo = wave_min(l), hi = wave_max(r);
+    if (idx < nvalid) { const PointRec &rc = W.srec[idx]; l = rc.l; r = rc.r; }
+    const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(idx < nvalid ? l : INT_MIN);
     if (lane == 0) {
         W.glo[g] = lo;
         W.ghi[g] = hi;
-        W.gcost[g] = hi >= lo ? group_total(group_cost(lo, hi, P.chunk, W.cost_shift)) : 0;
+        W.gml[g] = ml;
+        W.gcost[g] = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, P.chunk, W.cost_shift)) : 0;
     }
 }
 
@@ -330,24 +374,20 @@ __device__ __forceinline__ long long group_start(const EvalWs &W, int g) {
 }
 
 // per group: the wavefronts owning its first and last tiles
-__global__ __launch_bounds__(256) void k_part_groups(DevPlan P, EvalWs W) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= W.n_groups) return;
+__device__ __forceinline__ void part_group(const DevPlan &P, const EvalWs &W, int g) {
     const long long total = W.ctl[0];
     const int cost = W.gcost[g];
     if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
     const int NW = (int)W.n_waves;
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], P.chunk, W.cost_shift);
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], P.chunk, W.cost_shift);
     const long long A = group_start(W, g), B = A + cost;
     W.gwave[g] = make_int2((int)(A * NW / total), (int)((B - gc.last) * NW / total));
 }
 
 // per wavefront: its first tile as (group, chunk), or (group, -1) for "the first
 // tile of the first group with tiles at or after this one"; (G, 0) past the end
-__global__ __launch_bounds__(256) void k_part_waves(DevPlan P, EvalWs W) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void part_wave(const DevPlan &P, const EvalWs &W, int w) {
     const int G = (int)W.n_groups, NW = (int)W.n_waves, C = P.chunk;
-    if (w > NW) return;
     const long long total = W.ctl[0];
     const long long sw = ((long long)w * total + NW - 1) / NW;
     if (w == NW || total == 0 || sw >= total) { W.wstart[w] = make_int2(G, 0); return; }
@@ -360,22 +400,36 @@ __global__ __launch_bounds__(256) void k_part_waves(DevPlan P, EvalWs W) {
     const int g = lo;
     const long long A = group_start(W, g), B = A + W.gcost[g];
     if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], C, W.cost_shift);
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
     // the tile whose interval holds s_w, and its start
     int c;
     long long a;
     if (sw < A + gc.first || gc.chi == gc.clo) { c = gc.clo; a = A; }
     else if (sw >= B - gc.last) { c = gc.chi; a = B - gc.last; }
     else {
-        const long long q = (sw - A - gc.first) / gc.mid;
-        c = gc.clo + 1 + (int)q;
-        a = A + gc.first + q * gc.mid;
+        const long long x = sw - A - gc.first, xs = (long long)gc.ns * gc.cs;
+        if (x < xs) {
+            const long long q = x / gc.cs;
+            c = gc.clo + 1 + (int)q;
+            a = A + gc.first + q * gc.cs;
+        } else {
+            const long long q = (x - xs) / gc.cn;
+            c = gc.clo + 1 + gc.ns + (int)q;
+            a = A + gc.first + xs + q * gc.cn;
+        }
     }
     int2 st;
     if (a == sw) st = make_int2(g, c);
     else if (c < gc.chi) st = make_int2(g, c + 1);
     else st = make_int2(g + 1, -1);
     W.wstart[w] = st;
+}
+
+// threads [0, G): groups; threads [G, G + NW]: wavefronts and the end sentinel
+__global__ __launch_bounds__(256) void k_partition(DevPlan P, EvalWs W) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < W.n_groups) part_group(P, W, (int)i);
+    else if (i <= W.n_groups + W.n_waves) part_wave(P, W, (int)(i - W.n_groups));
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -504,6 +558,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
                                                            long long *__restrict__ e_out, EvalWs W) {
     const int lane = threadIdx.x % kWave;
     const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
+    // per lane: the chained w^(c C) and w^C, and the fixed-point sums of the
+    // segment (kept here, not in registers: they are touched once per tile)
+    __shared__ double s_ch[4][kWindowThreads];
+    __shared__ long long s_che[2][kWindowThreads];
+    __shared__ long long s_acc[4][kWindowThreads];    // fixed-point sums of the segment
     if (w >= W.n_waves) return;
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
@@ -539,12 +598,21 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
         const int seg_c0 = c;
         const int idx = g * kWave + lane;
         const bool valid = idx < nvalid;
-        const int l = valid ? W.sl[idx] : 1, r = valid ? W.sr[idx] : 0;
+        PointRec rc;
+        if (valid) rc = W.srec[idx];
+        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.eref = 0; }
+        const int l = rc.l, r = rc.r;
         const bool multi = valid && (l / C != r / C);
-        const double2 zz = valid ? W.sz[idx] : make_double2(0.0, 0.0);
-        const long long eref = multi ? W.seref[idx] : 0;
-        const double zr = zz.x, zi = zz.y;
-        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        // z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1) (a stand-in for lanes
+        // without a point); z itself is rebuilt exactly from w when needed
+        const int ez = valid ? exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y))) : 0;
+        const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
+        // w^(c C) for the lanes that entered the window in an earlier chunk,
+        // advanced by one product per chunk (cpow_chunk_start's recipe)
+        int chain_c = -1;                                 // chunk of the chained power; -1: none
+        bool have_zc = false;
+        bool xv = false;                                  // this lane's chained power is w^(chain_c C)
+        s_acc[0][threadIdx.x] = 0; s_acc[1][threadIdx.x] = 0; s_acc[2][threadIdx.x] = 0; s_acc[3][threadIdx.x] = 0;
         for (;;) {
             // ---- tile (g, c): this lane's part [lo, hi] of chunk c
             const int c0 = c * C, c1 = c0 + C - 1;
@@ -555,7 +623,56 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
             const int Ahi = __builtin_amdgcn_readfirstlane(wave_min(act ? hi : INT_MAX));
             const int Alo = __builtin_amdgcn_readfirstlane(wave_max(act ? lo : INT_MIN));
             if (Khi >= Klo) {
+                // z^lo first: w^l by binary powering where the window starts in this
+                // chunk, the chained w^(c C) where it started earlier
+                const bool cont = act && l < c0;
+                double pr = 1.0, pi = 0.0;
+                long long pe = 0;
+                const int t = threadIdx.x;
+                const bool any_cont = __ballot(cont) != 0;
+                // a continuing lane advances its chained power by one product if it
+                // holds w^((c - 1) C) and c is not an anchor; otherwise it starts
+                // from the anchor w^(m C), m = c - c mod kAnchor
+                const bool step_ok = chain_c >= 0 && chain_c == c - 1 && c % kAnchor != 0;
+                const bool use_chain = cont && xv && step_ok;
+                const bool need_anchor = cont && !use_chain;
+                // at most two rounds of one binary powering each (one call site keeps
+                // the register footprint down): round 0, once per segment, w^C;
+                // round 1, the anchors of continuing lanes that need them and w^lo of
+                // lanes whose window starts in this chunk
+                const bool need1 = __ballot(need_anchor || (!cont && act && lo > 0)) != 0;
+                const int rd_end = need1 ? 1 : 0;
+#pragma nounroll
+                for (int rd = (any_cont && !have_zc) ? 0 : 1; rd <= rd_end; ++rd) {
+                    const int n = rd == 0 ? C : (need_anchor ? (c - c % kAnchor) * C : (!cont && act ? lo : 0));
+                    double qr_, qi_;
+                    long long qe = 0;
+                    cpow_dd(wr, wi, n, qr_, qi_, qe);
+                    if (rd == 0) {
+                        s_ch[2][t] = qr_; s_ch[3][t] = qi_; s_che[1][t] = qe;
+                    } else {
+                        pr = qr_; pi = qi_; pe = qe;
+                    }
+                }
+                if (any_cont) {
+                    have_zc = true;
+                    if (cont) {
+                        const double zcr = s_ch[2][t], zci = s_ch[3][t];
+                        const long long zce = s_che[1][t];
+                        double xr, xi;
+                        long long xe;
+                        int j0;
+                        if (use_chain) { xr = s_ch[0][t]; xi = s_ch[1][t]; xe = s_che[0][t]; j0 = c - 1; }
+                        else { xr = pr; xi = pi; xe = pe; j0 = c - c % kAnchor; }
+                        for (int j = j0; j < c; ++j) cmul_renorm(xr, xi, xe, zcr, zci, zce);
+                        s_ch[0][t] = xr; s_ch[1][t] = xi; s_che[0][t] = xe;
+                        pr = xr; pi = xi; pe = xe;
+                    }
+                    xv = cont;
+                    chain_c = c;
+                }
                 double hr = 0.0, hi_ = 0.0;
+                const double zr = ldexp(wr, ez), zi = ldexp(wi, ez);
                 if (Ahi >= Alo) {
                     run_steps<kTop>(hr, hi_, zr, zi, cf, Khi, Ahi + 1, lo, hi);
                     run_steps<kAll>(hr, hi_, zr, zi, cf, Ahi, Alo, lo, hi);
@@ -564,14 +681,8 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
                     run_steps<kBoth>(hr, hi_, zr, zi, cf, Khi, Klo, lo, hi);
                 }
                 if (act) {
-                    // multiply by z^lo: z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1)
-                    long long E = P.coef_shift;
-                    double pr = 1.0, pi = 0.0;
-                    if (lo > 0) {
-                        const int ez = exp_of(fmax(fabs(zr), fabs(zi)));
-                        cpow_dd(ldexp(zr, -ez), ldexp(zi, -ez), lo, pr, pi, E);
-                        E += (long long)lo * ez;
-                    }
+                    // times z^lo = (pr + i pi) 2^(pe + lo ez)
+                    const long long E = P.coef_shift + pe + (long long)lo * ez;
                     const double qr = fma(hr, pr, -hi_ * pi);
                     const double qi = fma(hr, pi, hi_ * pr);
                     if (!multi) {
@@ -582,7 +693,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
                         m_out[j] = m;
                         e_out[j] = e;
                     } else {
-                        fix_add(P, qr, qi, E, eref, a0, a1, a2, a3);
+                        fix_add(P, qr, qi, E, W.srec[idx].eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
                     }
                 }
             }
@@ -594,10 +705,12 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
         // part of a group leaves its fixed-point sums in this wavefront's slot
         // (0: its first segment, 1: its last)
         if (multi) {
+            const int t = threadIdx.x;
+            const long long a0 = s_acc[0][t], a1 = s_acc[1][t], a2 = s_acc[2][t], a3 = s_acc[3][t];
             if (seg_c0 == clo && c == chi) {
                 double2 m;
                 long long e;
-                fix_out(P, a0, a1, a2, a3, eref, m, e);
+                fix_out(P, a0, a1, a2, a3, W.srec[idx].eref, m, e);
                 const int j = W.sperm[idx];
                 m_out[j] = m;
                 e_out[j] = e;
@@ -614,7 +727,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
 
 // Points whose window spans several chunks, in groups split across
 // wavefronts: the sum of the fixed-point partials the owning wavefronts left
-// in their slots.  One workgroup per group; its threads stride over the owning
+// in their slots.  One workgroup per such group; its threads stride over the owning
 // wavefronts (integer sums: the order does not matter).  The first owner may
 // hold the group as its last segment (slot 1); every later owner holds it as
 // its first segment (slot 0).
@@ -623,9 +736,14 @@ constexpr int kFinalThreads = 1024;
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out, EvalWs W) {
     __shared__ long long part[kFinalThreads / kWave][kWave][4];
-    const int g = blockIdx.x;
+    // a group owned by several wavefronts starts the range of the second one
+    // (inside the group: its first tile belongs to the first owner, its last
+    // tile to a later one), which identifies the group exactly once
+    const int w1 = blockIdx.x + 1;
+    const int g = W.wstart[w1].x;
+    if (W.wstart[w1].y < 0 || g >= W.n_groups) return;
     const int2 gw = W.gwave[g];
-    if (gw.x == gw.y) return;                        // written by its only wavefront
+    if (gw.x != w1 - 1) return;
     const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave, nq = kFinalThreads / kWave;
     int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
     resolve_tile(W, P.chunk, fg, fc);
@@ -642,10 +760,12 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
         a0 += part[k][lane][0]; a1 += part[k][lane][1]; a2 += part[k][lane][2]; a3 += part[k][lane][3];
     }
     const int p = g * kWave + lane;
-    if (p >= valid_points(W) || W.sl[p] / P.chunk == W.sr[p] / P.chunk) return;
+    if (p >= valid_points(W)) return;
+    const PointRec rc = W.srec[p];
+    if (rc.l / P.chunk == rc.r / P.chunk) return;
     double2 m;
     long long e;
-    fix_out(P, a0, a1, a2, a3, W.seref[p], m, e);
+    fix_out(P, a0, a1, a2, a3, rc.eref, m, e);
     const int j = W.sperm[p];
     m_out[j] = m;
     e_out[j] = e;
@@ -701,7 +821,8 @@ int cost_shift_for(const DevPlan &P, int64_t n) {
     for (int sh = 0; sh <= 20; ++sh) {
         const int64_t u = (int64_t)kCostUnit << sh;
         auto units = [u](int64_t steps) { return (steps + u - 1) / u; };
-        const int64_t bound = G * (chunks * (units(P.chunk) + units(kPowSteps * 31 + kTileSteps)) + units(kGroupSteps));
+        const int64_t per_tile = units(P.chunk + kTileSteps + kGroupSteps + kPowSteps * 31 * 2);
+        const int64_t bound = G * chunks * per_tile;
         if (bound < INT32_MAX) return sh;
     }
     return -1;
@@ -716,20 +837,16 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     const int64_t tlen = (int64_t)(kBins + 1) * NB;
     const int64_t nseg_t = (tlen + kSeg - 1) / kSeg, nseg_g = (G + kSeg - 1) / kSeg;
     EvalWs w;
-    w.ell = (int32_t *)take(sizeof(int32_t) * n);
-    w.rr = (int32_t *)take(sizeof(int32_t) * n);
-    w.eref = (long long *)take(sizeof(long long) * n);
+    w.rec = (PointRec *)take(sizeof(PointRec) * n);
     w.key = (int32_t *)take(sizeof(int32_t) * n);
+    w.srec = (PointRec *)take(sizeof(PointRec) * n);
     w.sperm = (int32_t *)take(sizeof(int32_t) * n);
-    w.sl = (int32_t *)take(sizeof(int32_t) * n);
-    w.sr = (int32_t *)take(sizeof(int32_t) * n);
-    w.seref = (long long *)take(sizeof(long long) * n);
-    w.sz = (double2 *)take(sizeof(double2) * n);
     w.table = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.tscan = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.bin_sum = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));
     w.bin_off = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));
     w.glo = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gml = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.ghi = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcost = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcum = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
@@ -784,22 +901,22 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     long long *e = reinterpret_cast<long long *>(e_dev);
     long long *win = reinterpret_cast<long long *>(window_dev);
     const int ni = (int)n;
-    const unsigned pb = (unsigned)((n + 255) / 256);
+    const unsigned bb = (unsigned)((n + kBoundsThreads - 1) / kBoundsThreads);
     const unsigned sb = (unsigned)W.n_sort_blocks;
     const unsigned gb = (unsigned)((W.n_groups + 15) / 16);
     const int64_t tlen = (int64_t)(kBins + 1) * W.n_sort_blocks;
 
     FPE_HIP_CHECK(device_setup());
-    k_plan<<<sb, kSortThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
+    k_bounds<<<bb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
     if (P.nh > 0) {
+        k_hist<<<sb, kSortThreads, 0, stream>>>(ni, W);
         k_scan_seg<<<(unsigned)((tlen + kSeg - 1) / kSeg), 1024, 0, stream>>>(W.table, W.tscan, tlen, W.bin_sum,
                                                                              W.bin_off, W.ctl + 4, W.ctl + 5);
-        k_scatter<<<sb, kSortThreads, 0, stream>>>(z, ni, W);
+        k_scatter<<<sb, kSortThreads, 0, stream>>>(ni, W);
         k_groups<<<gb, 1024, 0, stream>>>(P, W);
         k_scan_seg<<<(unsigned)((W.n_groups + kSeg - 1) / kSeg), 1024, 0, stream>>>(
             W.gcost, W.gcum, W.n_groups, W.gseg_sum, W.gseg_off, W.ctl + 6, W.ctl + 0);
-        k_part_groups<<<(unsigned)((W.n_groups + 255) / 256), 256, 0, stream>>>(P, W);
-        k_part_waves<<<(unsigned)((W.n_waves + 1 + 255) / 256), 256, 0, stream>>>(P, W);
+        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 255) / 256), 256, 0, stream>>>(P, W);
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (g_prof.on) {
@@ -812,7 +929,7 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
-        k_finalize<<<(unsigned)W.n_groups, kFinalThreads, 0, stream>>>(P, m, e, W);
+        if (W.n_waves > 1) k_finalize<<<(unsigned)(W.n_waves - 1), kFinalThreads, 0, stream>>>(P, m, e, W);
     }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");

@@ -36,18 +36,24 @@ struct DevPlan {
     double2 a0;               // a_0, returned at z = 0
 };
 
+// What the window kernel needs of one point: z, its window [l, r] and the
+// reference exponent eref (every kept term is below 2^eref in magnitude).
+struct __align__(16) PointRec {
+    double2 z;
+    int32_t l, r;
+    long long eref;
+};
+
 // Workspace of one evaluation of n points, carved from the caller's buffer.
 struct EvalWs {
-    int32_t *ell, *rr;            // window [l, r] per point, input order (l > r: finished)
-    long long *eref;              // reference exponent: every kept term is < 2^eref
-    int32_t *key;                 // lambda bin per point
-    int32_t *sperm;               // sorted records: input index,
-    int32_t *sl, *sr;             //   window,
-    long long *seref;             //   reference exponent,
-    double2 *sz;                  //   point
+    PointRec *rec;                // per point, input order (l > r: finished)
+    int32_t *key;                 // lambda bin per point, input order
+    PointRec *srec;               // records sorted by lambda bin
+    int32_t *sperm;               //   and their input indices
     int32_t *table, *tscan;       // (bin x sort block) counts, bin-major, and their scan
     int32_t *bin_sum, *bin_off;   // per 4096-entry segment of the table scan
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
+    int32_t *gml;                 //   largest window start,
     int32_t *gcost, *gcum;        //   work of its tiles and its segment-local exclusive scan,
     int2 *gwave;                  //   first and last window wavefront owning its tiles
     int32_t *gseg_sum, *gseg_off; // per 4096-entry segment of the group scan
@@ -165,6 +171,34 @@ __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, do
     E += ex;
     pr = x.rh + x.rl;
     pi = x.ih + x.il;
+}
+
+// x <- x y for complex doubles x = (xr + i xi) 2^xe and y = (yr + i yi) 2^ye,
+// both with max(|re|, |im|) in [1/2, 1), renormalised the same way; about two
+// roundings per component.
+__host__ __device__ __forceinline__ void cmul_renorm(double &xr, double &xi, long long &xe, double yr, double yi,
+                                                     long long ye) {
+    FPE_NO_CONTRACT
+    const double r = fma(xr, yr, -(xi * yi));
+    const double i = fma(xr, yi, xi * yr);
+    const int k = exp_of(fmax(fabs(r), fabs(i)));
+    xr = ldexp(r, -k);
+    xi = ldexp(i, -k);
+    xe += ye + k;
+}
+
+// w^(c C) by a fixed recipe, so that every caller gets the same bits: the
+// anchor w^(m C), m = c - c mod kAnchor, by cpow_dd, then (c mod kAnchor)
+// products by w^C (itself from cpow_dd), each rounded to double.  Relative
+// error below (3 kAnchor) 2^-53.
+constexpr int kAnchor = 8;
+
+__host__ __device__ __forceinline__ void cpow_chunk_start(double wr, double wi, int c, int C, double zcr, double zci,
+                                                          long long zce, double &xr, double &xi, long long &xe) {
+    const int m = c - c % kAnchor;
+    xe = 0;
+    cpow_dd(wr, wi, m * C, xr, xi, xe);
+    for (int j = m; j < c; ++j) cmul_renorm(xr, xi, xe, zcr, zci, zce);
 }
 
 // wave-wide reductions over the 64 lanes

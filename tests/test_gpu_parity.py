@@ -153,6 +153,27 @@ def test_long_windows_several_chunks(fpe):
     say(f"  max scaled error {worst:.3e}")
 
 
+def test_window_starts_across_chunks(fpe):
+    """Sparse lambda values: the 64 windows of a group start (or end) in many
+    different chunks, so lanes join a group's run of chunks at different tiles
+    and the per-lane z^lo bookkeeping is exercised chunk after chunk."""
+    d = 60_000
+    c = workloads.uniform_coeffs(d, 22)
+    rng = np.random.default_rng(8)
+    lam = np.concatenate([rng.uniform(0.002, 0.02, 768), -rng.uniform(0.002, 0.02, 768)])
+    z = 2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, lam.size))
+    say(f"eval sparse lambda d={d} n={len(z)}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    chunk = plan.info().chunk
+    assert len(np.unique(w[:, 0] // chunk)) > 40 and len(np.unique(w[:, 1] // chunk)) > 40
+    assert ((w[:, 1] // chunk) - (w[:, 0] // chunk) >= 8).sum() > 500
+    ref = oracle.precondition(c, 53).eval(z)
+    assert_windows(w, ref)
+    assert_normalised(m, e)
+    worst = assert_values(m, e, c, z)
+    say(f"  max scaled error {worst:.3e}")
+
+
 @pytest.mark.parametrize("kind", ["wide", "sparse_wide"])
 def test_wide_dynamic_range(fpe, kind):
     """|a_k| = 2^g, g ~ N(0, 40^2), dense and 1 % sparse: a cover with many slopes."""
