@@ -11,7 +11,10 @@ separately, as the paper does.
 Besides the JSON fields the driver reads, the line carries:
   roofline      the window kernel (the dominant kernel) against the FP64 vector
                 peak: algorithmic flops per launch / its average launch time
-                from HIP events recorded around it on its stream
+                from HIP events recorded around it on its stream; traffic is
+                the HBM bytes per launch recorded with rocprofv3 counters in
+                profiles/k_window_uniform_d1e6_traffic.txt, reported only while
+                the window kernel's sources are the ones those counters measured
   cpu_baseline  the oracle (plain C, FP64 plan + double-double window sum) on a
                 bounded sample of the same points, on the host's cores
   horner_gpu    the same-GPU Horner baseline over all points
@@ -32,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "evaluations/sec at d=1e6 (FPE vs GPU Horner), max rel err vs FP64 oracle"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_window_uniform_d1e6_traffic.txt")
+WINDOW_SOURCES = [os.path.join(ROOT, "paper_2211_06320_amd", "csrc", f) for f in ("fpe_eval.hip", "fpe_internal.h")]
 
 
 def log(msg: str) -> None:
@@ -49,6 +54,34 @@ def algorithmic_flops(terms, window) -> float:
     return float(8.0 * U.sum() + 6.0 * mults.sum())
 
 
+def window_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in WINDOW_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per window-kernel launch from the committed counter summary, or
+    None when it is missing, for another workload, or for other kernel sources."""
+    if workload != "uniform_d1e6" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("window_sources_sha256") != window_sources_sha256():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,8 +91,11 @@ def main() -> int:
     ap.add_argument("--horner-steps", type=int, default=2)
     ap.add_argument("--no-horner", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--check-sample", type=int, default=1000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (a kernel of known traffic, "
+                         "to scale hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -98,6 +134,15 @@ def main() -> int:
     for _ in range(args.warmup):
         plan.eval(z, out=out)
     torch.cuda.synchronize()
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes device to device")
+        del src, dst
     fpe.profile_read()
     fpe.profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -114,6 +159,7 @@ def main() -> int:
     value = n / (ms_per_step * 1e-3)
     win_avg_ms = win_ms / max(launches, 1)
     achieved = flops / (win_avg_ms * 1e-3) / 1e12
+    traffic = recorded_traffic(wl.name)
     log(f"eval {ms_per_step:.3f} ms/step ({value:.3e} evals/s); window kernel {win_avg_ms:.3f} ms, "
         f"{achieved:.2f} TFLOP/s algorithmic")
 
@@ -134,7 +180,7 @@ def main() -> int:
                    "coefficients": "Re, Im i.i.d. uniform[-1,1]", "points": "uniform on the Riemann sphere",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "k_window", "kernel_ms": win_avg_ms,
                      "algorithmic_flops": flops, "kept_terms": int(terms_np.sum())},
         "precondition_ms": pre_ms,

@@ -580,13 +580,12 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
     }
     resolve_tile(W, C, g, c);
     resolve_tile(W, C, ge, ce);
-    // a wavefront may own no tile (a tile's work can exceed one share); the
-    // finalize kernel still reads its slots, so they start at zero
-    {
+    // a wavefront may own no tile (a tile's work can exceed one share) and yet
+    // lie inside a split group's owner range, where the finalize kernel reads
+    // its slot 0; every other slot that kernel reads is written below
+    if (g == ge && c == ce) {
         long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * 4;
-        long long *s1 = W.slots + ((size_t)(2 * w + 1) * kWave + lane) * 4;
         s0[0] = 0; s0[1] = 0; s0[2] = 0; s0[3] = 0;
-        s1[0] = 0; s1[1] = 0; s1[2] = 0; s1[3] = 0;
     }
     bool first_segment = true;
     // one pass per group segment: the consecutive tiles of one group this
