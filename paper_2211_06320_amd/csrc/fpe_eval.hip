@@ -4,17 +4,17 @@
 // One evaluation is a chain of short kernels on one stream, without
 // device-scope atomics on the data path:
 //
-//   k_bounds     per point (one thread each): lambda = log2|z| (eq. defLambda),
-//                k_lambda and N = max(Ehat + lambda Id) (eq. defN) by binary
-//                search over the cover vertices staged in LDS, the window [l, r]
-//                (eq. def:LRN) by two binary searches and a linear solve, the
-//                term count, a reference exponent and a lambda bin; written as
-//                one 32-byte record per point
-//   k_hist       per sort block of 8192 points: an LDS histogram of the bins,
-//                written as one column of the (bin x block) count table
-//   k_scan_seg   exclusive scan of the count table in bin-major order
-//   k_scatter    counting-sort scatter of the records (LDS cursors) into
-//                lambda-bin order
+//   k_bounds     per point: lambda = log2|z| (eq. defLambda), k_lambda and
+//                N = max(Ehat + lambda Id) (eq. defN) by binary search over the
+//                cover vertices staged in LDS, the window [l, r] (eq. def:LRN) by
+//                two binary searches and a linear solve, the term count, a
+//                reference exponent and a lambda bin, written as one 32-byte
+//                record per point; per sort block of 2048 points, LDS counters
+//                give each point its rank within its bin and the block's row of
+//                the (block x bin) count table
+//   k_scan_table exclusive scan of the count table in bin-major order
+//   k_scatter    counting-sort scatter of the records into lambda-bin order,
+//                one thread per point
 //   k_groups     per group of 64 consecutive sorted points (one wavefront):
 //                the union of their windows and the work of its C-term chunks
 //   k_scan_seg, k_partition   an equal-work partition of the (group, chunk)
@@ -49,11 +49,10 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kBins = 4096;            // lambda bins; bin kBins holds finished points
-constexpr int kBoundsThreads = 1024;   // window kernel-independent per-point work: one point per thread
-constexpr int kSortThreads = 1024;     // histogram and scatter: kPerThread points per thread
-constexpr int kPerThread = 8;
-constexpr int kSortPoints = kSortThreads * kPerThread;
+constexpr int kBins = 2048;            // lambda bins; bin kBins holds finished points
+constexpr int kBoundsThreads = 1024;
+constexpr int kPerThread = 2;          // points per k_bounds thread
+constexpr int kSortPoints = kBoundsThreads * kPerThread;   // points per sort block (one k_bounds block)
 constexpr int kSeg = 4096;             // scan segment
 
 // lambda bin: a monotone map of lambda onto [0, kBins), finest near 0 where the
@@ -84,24 +83,11 @@ __device__ __forceinline__ int valid_points(const EvalWs &W) {
 // lambda Id) (eq. defN) by binary search over the cover vertices, the window
 // [l, r] (eq. def:LRN) by two binary searches and a linear solve, the reference
 // exponent and the lambda bin.  Points with no window (z = 0, a non-finite z,
-// P == 0) get their value here and the bin kBins.
-__global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const double2 *__restrict__ z, int n,
-                                                           double2 *__restrict__ m_out,
-                                                           long long *__restrict__ e_out,
-                                                           int32_t *__restrict__ terms,
-                                                           long long *__restrict__ win, EvalWs W) {
-    __shared__ double s_k[kHullLds];
-    __shared__ double s_s[kHullLds];
-    const int t = threadIdx.x;
-    if (blockIdx.x == 0 && t < 64) W.ctl[t] = 0;      // scan tickets and totals
-    const bool in_lds = P.nh <= kHullLds;
-    if (in_lds)
-        for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
-    __syncthreads();
-    const int j = blockIdx.x * kBoundsThreads + t;
-    if (j >= n) return;
-    const double *hk = in_lds ? s_k : P.hull_k;
-    const double *hs = in_lds ? s_s : P.hull_s;
+// P == 0) get their value here and the bin kBins.  Returns the bin.
+__device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, const double *hs,
+                                            const double2 *__restrict__ z, int j, double2 *__restrict__ m_out,
+                                            long long *__restrict__ e_out, int32_t *__restrict__ terms,
+                                            long long *__restrict__ win, const EvalWs &W) {
     const int nh = P.nh;
     const double2 zz = z[j];
     int32_t l = 1, r = 0, cnt = 0;                     // l > r: no window for the window kernel
@@ -176,45 +162,52 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
     rc.r = r;
     rc.eref = er;
     W.rec[j] = rc;
-    W.key[j] = key;
+    return key;
 }
 
-// Per sort block of kSortPoints consecutive points: the histogram of their
-// bins, written as one column of the (bin x block) count table.
-__global__ __launch_bounds__(kSortThreads) void k_hist(int n, EvalWs W) {
+// One sort block of kSortPoints consecutive points per workgroup: the points'
+// bounds and bins, each point's rank among the block's points of its bin (LDS
+// counters), and the block's bin counts, written as one row of the
+// (block x bin) count table.
+__global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const double2 *__restrict__ z, int n,
+                                                           double2 *__restrict__ m_out,
+                                                           long long *__restrict__ e_out,
+                                                           int32_t *__restrict__ terms,
+                                                           long long *__restrict__ win, EvalWs W) {
+    __shared__ double s_k[kHullLds];
+    __shared__ double s_s[kHullLds];
     __shared__ int32_t hist[kBins + 1];
     const int t = threadIdx.x, b = blockIdx.x;
-    for (int i = t; i <= kBins; i += kSortThreads) hist[i] = 0;
+    if (b == 0 && t < 64) W.ctl[t] = 0;               // scan tickets and totals
+    const bool in_lds = P.nh <= kHullLds;
+    if (in_lds)
+        for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+    for (int i = t; i <= kBins; i += kBoundsThreads) hist[i] = 0;
     __syncthreads();
-    int keys[kPerThread];
+    const double *hk = in_lds ? s_k : P.hull_k;
+    const double *hs = in_lds ? s_s : P.hull_s;
 #pragma unroll
     for (int it = 0; it < kPerThread; ++it) {
-        const int j = b * kSortPoints + it * kSortThreads + t;
-        keys[it] = j < n ? W.key[j] : -1;
+        const int j = b * kSortPoints + it * kBoundsThreads + t;
+        if (j < n) {
+            const int key = bounds_point(P, hk, hs, z, j, m_out, e_out, terms, win, W);
+            const int rank = atomicAdd(&hist[key], 1);  // LDS
+            W.keyrank[j] = key * kSortPoints + rank;
+        }
     }
-#pragma unroll
-    for (int it = 0; it < kPerThread; ++it)
-        if (keys[it] >= 0) atomicAdd(&hist[keys[it]], 1);     // LDS
     __syncthreads();
-    for (int i = t; i <= kBins; i += kSortThreads) W.table[(size_t)i * W.n_sort_blocks + b] = hist[i];
+    for (int i = t; i <= kBins; i += kBoundsThreads) W.table[(size_t)b * (kBins + 1) + i] = hist[i];
 }
 
-// Exclusive scan of int32 values in segments of kSeg = 4096 (1024 threads x 4,
-// coalesced 16-byte loads).  Every block scans its segment and writes the
-// segment-local exclusive prefix to out and the segment total to seg_sum; the
-// last block to finish (ticket) scans the totals into seg_off.  A global prefix
-// is out[i] + seg_off[i / kSeg].
-__device__ int32_t block_scan_seg(const int32_t *in, int32_t *out, int n, int32_t carry) {
+// Exclusive scan of int32 values in segments of kSeg = 4096 (1024 threads x 4).
+// Every block scans its segment and writes the segment-local exclusive prefix
+// to out and the segment total to seg_sum; the last block to finish (ticket)
+// scans the totals into seg_off.  A global prefix is out[i] + seg_off[i / kSeg].
+// v: this thread's 4 consecutive values (zero past n); out: the segment's output.
+__device__ int32_t block_scan4(const int32_t v[4], int32_t *out, int n, int32_t carry) {
     __shared__ int32_t wsum[16];
     const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
-    int32_t v[4];
     const int i0 = 4 * t;
-    if (i0 + 3 < n && ((reinterpret_cast<uintptr_t>(in) & 15) == 0)) {
-        int4 q = reinterpret_cast<const int4 *>(in)[t];
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-        for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n) ? in[i0 + k] : 0;
-    }
     const int32_t s1 = v[0] + v[1], s2 = s1 + v[2], tot = s2 + v[3];
     int32_t x = tot;
     for (int o = 1; o < kWave; o <<= 1) {
@@ -241,16 +234,22 @@ __device__ int32_t block_scan_seg(const int32_t *in, int32_t *out, int n, int32_
     return block_total;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                   int64_t count, int32_t *__restrict__ seg_sum,
-                                                   int32_t *__restrict__ seg_off, int32_t *__restrict__ ticket,
-                                                   int32_t *__restrict__ total) {
+__device__ __forceinline__ void load4(const int32_t *in, int n, int32_t v[4]) {
+    const int i0 = 4 * threadIdx.x;
+    if (i0 + 3 < n && ((reinterpret_cast<uintptr_t>(in) & 15) == 0)) {
+        const int4 q = reinterpret_cast<const int4 *>(in)[threadIdx.x];
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n) ? in[i0 + k] : 0;
+    }
+}
+
+// the last block: scan of the segment totals
+__device__ void scan_segment_sums(int nseg, int32_t *__restrict__ seg_sum, int32_t *__restrict__ seg_off,
+                                  int32_t *__restrict__ ticket, int32_t *__restrict__ total, int32_t tot) {
     __shared__ int last;
-    const int b = blockIdx.x, nseg = gridDim.x;
-    const int64_t base = (int64_t)b * kSeg;
-    const int32_t tot = block_scan_seg(in + base, out + base, (int)min((int64_t)kSeg, count - base), 0);
     if (threadIdx.x == 0) {
-        seg_sum[b] = tot;
+        seg_sum[blockIdx.x] = tot;
         __threadfence();
         last = atomicAdd(ticket, 1) == nseg - 1;
     }
@@ -258,37 +257,56 @@ __global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ i
     if (!last) return;
     __threadfence();
     int32_t carry = 0;
-    for (int s0 = 0; s0 < nseg; s0 += kSeg)
-        carry += block_scan_seg(seg_sum + s0, seg_off + s0, min(kSeg, nseg - s0), carry);
+    for (int s0 = 0; s0 < nseg; s0 += kSeg) {
+        int32_t v[4];
+        load4(seg_sum + s0, min(kSeg, nseg - s0), v);
+        carry += block_scan4(v, seg_off + s0, min(kSeg, nseg - s0), carry);
+    }
     if (threadIdx.x == 0) *total = carry;
 }
 
-// Counting-sort scatter of the point records: bin-major positions from the
-// table scan, handed out within a block through LDS cursors.  Points of a bin
-// that share a block land in an unspecified order; results do not depend on it.
-__global__ __launch_bounds__(kSortThreads) void k_scatter(int n, EvalWs W) {
-    __shared__ int32_t cur[kBins + 1];
-    const int t = threadIdx.x, b = blockIdx.x;
-    for (int i = t; i <= kBins; i += kSortThreads) {
-        const int64_t idx = (int64_t)i * W.n_sort_blocks + b;
-        cur[i] = W.tscan[idx] + W.bin_off[idx / kSeg];
+__global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                   int64_t count, int32_t *__restrict__ seg_sum,
+                                                   int32_t *__restrict__ seg_off, int32_t *__restrict__ ticket,
+                                                   int32_t *__restrict__ total) {
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int n = (int)min((int64_t)kSeg, count - base);
+    int32_t v[4];
+    load4(in + base, n, v);
+    const int32_t tot = block_scan4(v, out + base, n, 0);
+    scan_segment_sums(gridDim.x, seg_sum, seg_off, ticket, total, tot);
+}
+
+// The count table is stored by block (row b holds the block's kBins + 1 bin
+// counts) and scanned in bin-major order, entry (bin i, block b) at position
+// i NB + b: all points of bin 0, block by block, then bin 1, ...
+__global__ __launch_bounds__(1024) void k_scan_table(EvalWs W) {
+    const int64_t NB = W.n_sort_blocks, count = (int64_t)(kBins + 1) * NB;
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int n = (int)min((int64_t)kSeg, count - base);
+    int32_t v[4];
+    for (int k = 0; k < 4; ++k) {
+        const int64_t jj = base + 4 * threadIdx.x + k;
+        v[k] = 4 * (int)threadIdx.x + k < n ? W.table[(jj % NB) * (kBins + 1) + jj / NB] : 0;
     }
-    int keys[kPerThread];
-#pragma unroll
-    for (int it = 0; it < kPerThread; ++it) {
-        const int j = b * kSortPoints + it * kSortThreads + t;
-        keys[it] = j < n ? W.key[j] : kBins;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < kPerThread; ++it) {
-        if (keys[it] == kBins) continue;               // finished points are not sorted
-        const int j = b * kSortPoints + it * kSortThreads + t;
-        const PointRec rc = W.rec[j];
-        const int pos = atomicAdd(&cur[keys[it]], 1);  // LDS
-        W.srec[pos] = rc;
-        W.sperm[pos] = j;
-    }
+    const int32_t tot = block_scan4(v, W.tscan + base, n, 0);
+    scan_segment_sums(gridDim.x, W.bin_sum, W.bin_off, W.ctl + 4, W.ctl + 5, tot);
+}
+
+// Counting-sort scatter of the point records, one thread per point: the
+// position is the bin-major prefix of the point's (bin, sort block) entry plus
+// its rank within that entry.  Points of a bin that share a sort block land in
+// an unspecified order; results do not depend on it.
+__global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
+    const int j = blockIdx.x * 1024 + threadIdx.x;
+    if (j >= n) return;
+    const int kr = W.keyrank[j];
+    const int key = kr / kSortPoints, rank = kr % kSortPoints;
+    if (key == kBins) return;                          // finished points are not sorted
+    const int64_t idx = (int64_t)key * W.n_sort_blocks + j / kSortPoints;
+    const int pos = W.tscan[idx] + W.bin_off[idx / kSeg] + rank;
+    W.srec[pos] = W.rec[j];
+    W.sperm[pos] = j;
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
@@ -726,11 +744,12 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
 
 // Points whose window spans several chunks, in groups split across
 // wavefronts: the sum of the fixed-point partials the owning wavefronts left
-// in their slots.  One workgroup per such group; its threads stride over the owning
-// wavefronts (integer sums: the order does not matter).  The first owner may
-// hold the group as its last segment (slot 1); every later owner holds it as
-// its first segment (slot 0).
+// in their slots.  One workgroup per such group; its threads stride over the
+// owning wavefronts (integer sums: the order does not matter).  The first owner
+// may hold the group as its last segment (slot 1); every later owner holds it
+// as its first segment (slot 0).
 constexpr int kFinalThreads = 1024;
+constexpr int kFinalUnroll = 1;   // owners' slots in flight per thread
 
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out, EvalWs W) {
@@ -748,9 +767,26 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
     resolve_tile(W, P.chunk, fg, fc);
     const int side0 = fg == g ? 0 : 1;
     long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    for (int w = gw.x + q; w <= gw.y; w += nq) {
-        const long long *slot = W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4;
-        a0 += slot[0]; a1 += slot[1]; a2 += slot[2]; a3 += slot[3];
+    auto slot_of = [&](int w) {
+        return reinterpret_cast<const longlong2 *>(W.slots +
+                                                   ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4);
+    };
+    int w = gw.x + q;
+    for (; w + (kFinalUnroll - 1) * nq <= gw.y; w += kFinalUnroll * nq) {
+        longlong2 x[kFinalUnroll][2];
+#pragma unroll
+        for (int u = 0; u < kFinalUnroll; ++u) {
+            const longlong2 *sl = slot_of(w + u * nq);
+            x[u][0] = sl[0];
+            x[u][1] = sl[1];
+        }
+#pragma unroll
+        for (int u = 0; u < kFinalUnroll; ++u) { a0 += x[u][0].x; a1 += x[u][0].y; a2 += x[u][1].x; a3 += x[u][1].y; }
+    }
+    for (; w <= gw.y; w += nq) {
+        const longlong2 *sl = slot_of(w);
+        const longlong2 x0 = sl[0], x1 = sl[1];
+        a0 += x0.x; a1 += x0.y; a2 += x1.x; a3 += x1.y;
     }
     part[q][lane][0] = a0; part[q][lane][1] = a1; part[q][lane][2] = a2; part[q][lane][3] = a3;
     __syncthreads();
@@ -837,7 +873,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     const int64_t nseg_t = (tlen + kSeg - 1) / kSeg, nseg_g = (G + kSeg - 1) / kSeg;
     EvalWs w;
     w.rec = (PointRec *)take(sizeof(PointRec) * n);
-    w.key = (int32_t *)take(sizeof(int32_t) * n);
+    w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
     w.srec = (PointRec *)take(sizeof(PointRec) * n);
     w.sperm = (int32_t *)take(sizeof(int32_t) * n);
     w.table = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
@@ -900,18 +936,16 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     long long *e = reinterpret_cast<long long *>(e_dev);
     long long *win = reinterpret_cast<long long *>(window_dev);
     const int ni = (int)n;
-    const unsigned bb = (unsigned)((n + kBoundsThreads - 1) / kBoundsThreads);
     const unsigned sb = (unsigned)W.n_sort_blocks;
+    const unsigned pb = (unsigned)((n + 1023) / 1024);
     const unsigned gb = (unsigned)((W.n_groups + 15) / 16);
     const int64_t tlen = (int64_t)(kBins + 1) * W.n_sort_blocks;
 
     FPE_HIP_CHECK(device_setup());
-    k_bounds<<<bb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
+    k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
     if (P.nh > 0) {
-        k_hist<<<sb, kSortThreads, 0, stream>>>(ni, W);
-        k_scan_seg<<<(unsigned)((tlen + kSeg - 1) / kSeg), 1024, 0, stream>>>(W.table, W.tscan, tlen, W.bin_sum,
-                                                                             W.bin_off, W.ctl + 4, W.ctl + 5);
-        k_scatter<<<sb, kSortThreads, 0, stream>>>(ni, W);
+        k_scan_table<<<(unsigned)((tlen + kSeg - 1) / kSeg), 1024, 0, stream>>>(W);
+        k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
         k_groups<<<gb, 1024, 0, stream>>>(P, W);
         k_scan_seg<<<(unsigned)((W.n_groups + kSeg - 1) / kSeg), 1024, 0, stream>>>(
             W.gcost, W.gcum, W.n_groups, W.gseg_sum, W.gseg_off, W.ctl + 6, W.ctl + 0);

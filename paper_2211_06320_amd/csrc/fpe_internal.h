@@ -47,10 +47,10 @@ struct __align__(16) PointRec {
 // Workspace of one evaluation of n points, carved from the caller's buffer.
 struct EvalWs {
     PointRec *rec;                // per point, input order (l > r: finished)
-    int32_t *key;                 // lambda bin per point, input order
+    int32_t *keyrank;             // per point, input order: lambda bin x (points per sort block) + rank
     PointRec *srec;               // records sorted by lambda bin
     int32_t *sperm;               //   and their input indices
-    int32_t *table, *tscan;       // (bin x sort block) counts, bin-major, and their scan
+    int32_t *table, *tscan;       // (sort block x bin) counts, and their bin-major scan
     int32_t *bin_sum, *bin_off;   // per 4096-entry segment of the table scan
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
     int32_t *gml;                 //   largest window start,
