@@ -76,7 +76,7 @@ __device__ __forceinline__ void normalise(double re, double im, long long E, dou
 // global exclusive prefix of the finished-points bin = number of points with a window
 __device__ __forceinline__ int valid_points(const EvalWs &W) {
     const int64_t idx = (int64_t)kBins * W.n_sort_blocks;
-    return W.tscan[idx] + W.bin_off[idx / kSeg];
+    return W.tscan[idx] + W.bin_off[kBins / W.tab_ib];
 }
 
 // Per point: lambda = log2|z| (eq. defLambda), k_lambda and N = max(Ehat +
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
     __shared__ double s_s[kHullLds];
     __shared__ int32_t hist[kBins + 1];
     const int t = threadIdx.x, b = blockIdx.x;
-    if (b == 0 && t < 64) W.ctl[t] = 0;               // scan tickets and totals
+    if (b == 0 && t < 64) W.ctl[t] = 0;               // totals, written by the scans
     const bool in_lds = P.nh <= kHullLds;
     if (in_lds)
         for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
@@ -201,8 +201,8 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
 
 // Exclusive scan of int32 values in segments of kSeg = 4096 (1024 threads x 4).
 // Every block scans its segment and writes the segment-local exclusive prefix
-// to out and the segment total to seg_sum; the last block to finish (ticket)
-// scans the totals into seg_off.  A global prefix is out[i] + seg_off[i / kSeg].
+// to out and the segment total to seg_sum; k_scan_sums then scans the totals
+// into seg_off.  A global prefix is out[i] + seg_off[i / kSeg].
 // v: this thread's 4 consecutive values (zero past n); out: the segment's output.
 __device__ int32_t block_scan4(const int32_t v[4], int32_t *out, int n, int32_t carry) {
     __shared__ int32_t wsum[16];
@@ -244,18 +244,22 @@ __device__ __forceinline__ void load4(const int32_t *in, int n, int32_t v[4]) {
     }
 }
 
-// the last block: scan of the segment totals
-__device__ void scan_segment_sums(int nseg, int32_t *__restrict__ seg_sum, int32_t *__restrict__ seg_off,
-                                  int32_t *__restrict__ ticket, int32_t *__restrict__ total, int32_t tot) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        seg_sum[blockIdx.x] = tot;
-        __threadfence();
-        last = atomicAdd(ticket, 1) == nseg - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+__global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                   int64_t count, int32_t *__restrict__ seg_sum) {
+    const int64_t base = (int64_t)blockIdx.x * kSeg;
+    const int n = (int)min((int64_t)kSeg, count - base);
+    int32_t v[4];
+    load4(in + base, n, v);
+    const int32_t tot = block_scan4(v, out + base, n, 0);
+    if (threadIdx.x == 0) seg_sum[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the nseg segment totals into seg_off, and
+// the grand total.  (A separate launch rather than a last-workgroup ticket: a
+// device-scope fence between workgroups would have to write back the L2 of
+// each XCD.)
+__global__ __launch_bounds__(1024) void k_scan_sums(const int32_t *__restrict__ seg_sum, int nseg,
+                                                    int32_t *__restrict__ seg_off, int32_t *__restrict__ total) {
     int32_t carry = 0;
     for (int s0 = 0; s0 < nseg; s0 += kSeg) {
         int32_t v[4];
@@ -265,32 +269,32 @@ __device__ void scan_segment_sums(int nseg, int32_t *__restrict__ seg_sum, int32
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_seg(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                   int64_t count, int32_t *__restrict__ seg_sum,
-                                                   int32_t *__restrict__ seg_off, int32_t *__restrict__ ticket,
-                                                   int32_t *__restrict__ total) {
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
-    const int n = (int)min((int64_t)kSeg, count - base);
-    int32_t v[4];
-    load4(in + base, n, v);
-    const int32_t tot = block_scan4(v, out + base, n, 0);
-    scan_segment_sums(gridDim.x, seg_sum, seg_off, ticket, total, tot);
-}
-
 // The count table is stored by block (row b holds the block's kBins + 1 bin
 // counts) and scanned in bin-major order, entry (bin i, block b) at position
-// i NB + b: all points of bin 0, block by block, then bin 1, ...
+// i NB + b: all points of bin 0, block by block, then bin 1, ...  Workgroup s
+// scans the bins [s Ib, (s + 1) Ib), Ib = max(1, kSeg / NB): it reads each
+// block row's Ib counts as one piece (coalesced) into LDS in bin-major order,
+// in passes of at most kSeg entries (several only when NB > kSeg).  A global
+// prefix is tscan[i NB + b] + bin_off[i / Ib].
 __global__ __launch_bounds__(1024) void k_scan_table(EvalWs W) {
-    const int64_t NB = W.n_sort_blocks, count = (int64_t)(kBins + 1) * NB;
-    const int64_t base = (int64_t)blockIdx.x * kSeg;
-    const int n = (int)min((int64_t)kSeg, count - base);
-    int32_t v[4];
-    for (int k = 0; k < 4; ++k) {
-        const int64_t jj = base + 4 * threadIdx.x + k;
-        v[k] = 4 * (int)threadIdx.x + k < n ? W.table[(jj % NB) * (kBins + 1) + jj / NB] : 0;
+    __shared__ int32_t tile[kSeg];
+    const int NB = (int)W.n_sort_blocks, K1 = kBins + 1, Ib = W.tab_ib;
+    const int i0 = blockIdx.x * Ib, ni = min(Ib, K1 - i0);
+    const int rows = kSeg / ni;                        // block rows per pass
+    int32_t carry = 0;
+    for (int b0 = 0; b0 < NB; b0 += rows) {
+        const int nb = min(rows, NB - b0), cnt = ni * nb;
+        for (int idx = threadIdx.x; idx < cnt; idx += 1024) {
+            const int b = idx / ni, ii = idx % ni;
+            tile[ii * nb + b] = W.table[(size_t)(b0 + b) * K1 + i0 + ii];
+        }
+        __syncthreads();
+        int32_t v[4];
+        for (int k = 0; k < 4; ++k) v[k] = 4 * (int)threadIdx.x + k < cnt ? tile[4 * threadIdx.x + k] : 0;
+        // one pass covers whole bins (nb == NB) or one bin (ni == 1): contiguous output
+        carry += block_scan4(v, W.tscan + (size_t)i0 * NB + b0, cnt, carry);
     }
-    const int32_t tot = block_scan4(v, W.tscan + base, n, 0);
-    scan_segment_sums(gridDim.x, W.bin_sum, W.bin_off, W.ctl + 4, W.ctl + 5, tot);
+    if (threadIdx.x == 0) W.bin_sum[blockIdx.x] = carry;
 }
 
 // Counting-sort scatter of the point records, one thread per point: the
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
     const int key = kr / kSortPoints, rank = kr % kSortPoints;
     if (key == kBins) return;                          // finished points are not sorted
     const int64_t idx = (int64_t)key * W.n_sort_blocks + j / kSortPoints;
-    const int pos = W.tscan[idx] + W.bin_off[idx / kSeg] + rank;
+    const int pos = W.tscan[idx] + W.bin_off[key / W.tab_ib] + rank;
     W.srec[pos] = W.rec[j];
     W.sperm[pos] = j;
 }
@@ -323,6 +327,15 @@ constexpr int kPowSteps = 10;
 constexpr int kTileSteps = 8;
 constexpr int kGroupSteps = 64;
 
+// floor(a / b) for 0 <= a < 2^62, 0 < b < 2^31 (quotients here fit in int32):
+// a double quotient, corrected exactly
+__device__ __forceinline__ long long div_floor(long long a, long long b) {
+    long long q = (long long)((double)a / (double)b);
+    while (q * b > a) --q;
+    while ((q + 1) * b <= a) ++q;
+    return q;
+}
+
 struct GroupCost {
     int clo, chi;              // first and last chunk of the group's union window
     int first, last;           // cost of its first and last tiles (first: the whole group if clo == chi)
@@ -331,8 +344,8 @@ struct GroupCost {
 };
 
 __device__ __forceinline__ int cost_units(int steps, int shift) {
-    const int u = kCostUnit << shift;
-    return (steps + u - 1) / u;
+    const int lg = 4 + shift;                          // kCostUnit = 16 = 2^4
+    return (steps + (1 << lg) - 1) >> lg;
 }
 
 __device__ __forceinline__ int bit_length(int x) { return x > 0 ? 32 - __clz(x) : 0; }
@@ -391,63 +404,64 @@ __device__ __forceinline__ long long group_start(const EvalWs &W, int g) {
     return (long long)W.gcum[g] + W.gseg_off[g / kSeg];
 }
 
-// per group: the wavefronts owning its first and last tiles
-__device__ __forceinline__ void part_group(const DevPlan &P, const EvalWs &W, int g) {
-    const long long total = W.ctl[0];
-    const int cost = W.gcost[g];
-    if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
-    const int NW = (int)W.n_waves;
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], P.chunk, W.cost_shift);
-    const long long A = group_start(W, g), B = A + cost;
-    W.gwave[g] = make_int2((int)(A * NW / total), (int)((B - gc.last) * NW / total));
-}
-
-// per wavefront: its first tile as (group, chunk), or (group, -1) for "the first
-// tile of the first group with tiles at or after this one"; (G, 0) past the end
-__device__ __forceinline__ void part_wave(const DevPlan &P, const EvalWs &W, int w) {
-    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = P.chunk;
-    const long long total = W.ctl[0];
-    const long long sw = ((long long)w * total + NW - 1) / NW;
-    if (w == NW || total == 0 || sw >= total) { W.wstart[w] = make_int2(G, 0); return; }
-    // the last group starting at or before s_w
-    int lo = 0, hi = G - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (group_start(W, mid) <= sw) lo = mid; else hi = mid - 1;
-    }
-    const int g = lo;
-    const long long A = group_start(W, g), B = A + W.gcost[g];
-    if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
-    // the tile whose interval holds s_w, and its start
+// the first tile of wavefront w, whose start s lies in group g's interval
+// [A, B) of the cost axis: (g, c) if a tile of g starts exactly at s, else
+// (g, c + 1) for the tile after the one holding s, or (g + 1, -1) for "the
+// first tile of the first group with tiles after g"
+__device__ __forceinline__ int2 wave_start(const GroupCost &gc, int g, long long A, long long B, long long s) {
     int c;
     long long a;
-    if (sw < A + gc.first || gc.chi == gc.clo) { c = gc.clo; a = A; }
-    else if (sw >= B - gc.last) { c = gc.chi; a = B - gc.last; }
+    if (s < A + gc.first || gc.chi == gc.clo) { c = gc.clo; a = A; }
+    else if (s >= B - gc.last) { c = gc.chi; a = B - gc.last; }
     else {
-        const long long x = sw - A - gc.first, xs = (long long)gc.ns * gc.cs;
+        const long long x = s - A - gc.first, xs = (long long)gc.ns * gc.cs;
         if (x < xs) {
-            const long long q = x / gc.cs;
+            const long long q = div_floor(x, gc.cs);
             c = gc.clo + 1 + (int)q;
             a = A + gc.first + q * gc.cs;
         } else {
-            const long long q = (x - xs) / gc.cn;
+            const long long q = div_floor(x - xs, gc.cn);
             c = gc.clo + 1 + gc.ns + (int)q;
             a = A + gc.first + xs + q * gc.cn;
         }
     }
-    int2 st;
-    if (a == sw) st = make_int2(g, c);
-    else if (c < gc.chi) st = make_int2(g, c + 1);
-    else st = make_int2(g + 1, -1);
-    W.wstart[w] = st;
+    if (a == s) return make_int2(g, c);
+    if (c < gc.chi) return make_int2(g, c + 1);
+    return make_int2(g + 1, -1);
 }
 
-// threads [0, G): groups; threads [G, G + NW]: wavefronts and the end sentinel
+// One wavefront per group: the owners of the group's first and last tiles,
+// and the first tile of every window wavefront whose start s_w falls in the
+// group's interval (a group may hold hundreds: the lanes share them out).
+// Wavefront G of the grid sets the wavefronts whose start lies past the end
+// of the work, and the sentinel w = NW, to (G, 0).
 __global__ __launch_bounds__(256) void k_partition(DevPlan P, EvalWs W) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < W.n_groups) part_group(P, W, (int)i);
-    else if (i <= W.n_groups + W.n_waves) part_wave(P, W, (int)(i - W.n_groups));
+    const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int G = (int)W.n_groups, NW = (int)W.n_waves;
+    const long long total = W.ctl[0];
+    if (g > G) return;
+    if (g == G) {
+        // the first wavefront whose start s_w = ceil(w total / NW) reaches total
+        const int wend = total > 0 ? (int)min((long long)NW, div_floor((total - 1) * NW, total) + 1) : 0;
+        for (int w = wend + lane; w <= NW; w += kWave) W.wstart[w] = make_int2(G, 0);
+        return;
+    }
+    const int cost = W.gcost[g];
+    if (cost == 0 || total == 0) {
+        if (lane == 0) W.gwave[g] = make_int2(-1, -1);
+        return;
+    }
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], P.chunk, W.cost_shift);
+    const long long A = group_start(W, g), B = A + cost;
+    if (lane == 0) W.gwave[g] = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
+    // wavefronts with A <= s_w < B
+    const int w0 = A == 0 ? 0 : (int)div_floor((A - 1) * NW, total) + 1;
+    const int w1 = (int)div_floor((B - 1) * NW, total);
+    for (int w = w0 + lane; w <= w1 && w < NW; w += kWave) {
+        const long long sw = div_floor((long long)w * total + NW - 1, NW);
+        W.wstart[w] = wave_start(gc, g, A, B, sw);
+    }
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -870,7 +884,8 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     const int64_t G = (n + kWave - 1) / kWave;
     const int64_t NB = (n + kSortPoints - 1) / kSortPoints;
     const int64_t tlen = (int64_t)(kBins + 1) * NB;
-    const int64_t nseg_t = (tlen + kSeg - 1) / kSeg, nseg_g = (G + kSeg - 1) / kSeg;
+    const int tab_ib = NB <= kSeg ? (int)(kSeg / (NB > 0 ? NB : 1)) : 1;
+    const int64_t nseg_t = (kBins + 1 + tab_ib - 1) / tab_ib, nseg_g = (G + kSeg - 1) / kSeg;
     EvalWs w;
     w.rec = (PointRec *)take(sizeof(PointRec) * n);
     w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
@@ -893,6 +908,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     w.slots = (long long *)take(sizeof(long long) * 4 * kWave * 2 * w.n_waves);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
+    w.tab_ib = tab_ib;
     w.cost_shift = cost_shift_for(P, n);
     w.n_groups = G;
     w.n_sort_blocks = NB;
@@ -939,17 +955,19 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     const unsigned sb = (unsigned)W.n_sort_blocks;
     const unsigned pb = (unsigned)((n + 1023) / 1024);
     const unsigned gb = (unsigned)((W.n_groups + 15) / 16);
-    const int64_t tlen = (int64_t)(kBins + 1) * W.n_sort_blocks;
 
     FPE_HIP_CHECK(device_setup());
     k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
     if (P.nh > 0) {
-        k_scan_table<<<(unsigned)((tlen + kSeg - 1) / kSeg), 1024, 0, stream>>>(W);
+        const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
+        k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
+        k_scan_sums<<<1, 1024, 0, stream>>>(W.bin_sum, nseg_t, W.bin_off, W.ctl + 5);
         k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
         k_groups<<<gb, 1024, 0, stream>>>(P, W);
-        k_scan_seg<<<(unsigned)((W.n_groups + kSeg - 1) / kSeg), 1024, 0, stream>>>(
-            W.gcost, W.gcum, W.n_groups, W.gseg_sum, W.gseg_off, W.ctl + 6, W.ctl + 0);
-        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 255) / 256), 256, 0, stream>>>(P, W);
+        const int nseg_g = (int)((W.n_groups + kSeg - 1) / kSeg);
+        k_scan_seg<<<(unsigned)nseg_g, 1024, 0, stream>>>(W.gcost, W.gcum, W.n_groups, W.gseg_sum);
+        k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg_g, W.gseg_off, W.ctl + 0);
+        k_partition<<<(unsigned)((W.n_groups + 1 + 3) / 4), 256, 0, stream>>>(P, W);
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (g_prof.on) {

@@ -51,7 +51,7 @@ struct EvalWs {
     PointRec *srec;               // records sorted by lambda bin
     int32_t *sperm;               //   and their input indices
     int32_t *table, *tscan;       // (sort block x bin) counts, and their bin-major scan
-    int32_t *bin_sum, *bin_off;   // per 4096-entry segment of the table scan
+    int32_t *bin_sum, *bin_off;   // per table-scan segment (tab_ib bins)
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
     int32_t *gml;                 //   largest window start,
     int32_t *gcost, *gcum;        //   work of its tiles and its segment-local exclusive scan,
@@ -59,9 +59,10 @@ struct EvalWs {
     int32_t *gseg_sum, *gseg_off; // per 4096-entry segment of the group scan
     int2 *wstart;                 // per window wavefront: first tile (group, chunk); n_waves + 1
     long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
-    int32_t *ctl;                 // [0] total work, [4] [6] scan tickets, [5] sorted points
+    int32_t *ctl;                 // [0] total tile work, [5] points in the count table
     int64_t n, n_groups, n_sort_blocks, n_waves;
     int32_t cost_shift;           // tile work is counted in units of (16 << cost_shift) steps
+    int32_t tab_ib;               // bins per table-scan segment
 };
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base);
@@ -112,26 +113,32 @@ __host__ __device__ __forceinline__ void cdd_renorm(CDD &x, long long &E) {
     E += k;
 }
 
-// x^2 for a complex double-double x
+// x^2 for a complex double-double x.  The last sum of each component is a
+// Fast2Sum: exact when the first operand is the larger one, and otherwise
+// (heavy cancellation in Re x^2) off by at most an ulp of that small
+// component, far below 2^-100 |x|^2.
 __host__ __device__ __forceinline__ CDD cdd_sqr(const CDD &x) {
     FPE_NO_CONTRACT
+    const double rh2 = x.rh + x.rh;                  // exact
     double p1 = x.rh * x.rh;
     double e1 = fma(x.rh, x.rh, -p1);
-    e1 = fma(x.rh + x.rh, x.rl, e1);
+    e1 = fma(rh2, x.rl, e1);
     double p2 = x.ih * x.ih;
     double e2 = fma(x.ih, x.ih, -p2);
     e2 = fma(x.ih + x.ih, x.il, e2);
     dd2 s = two_sum(p1, -p2);
-    dd2 re = two_sum(s.hi, s.lo + (e1 - e2));
-    double q = x.rh * x.ih;
-    double eq = fma(x.rh, x.ih, -q);
-    eq = fma(x.rh, x.il, eq);
-    eq = fma(x.rl, x.ih, eq);
-    dd2 im = two_sum(q, eq);
-    return {re.hi, re.lo, 2.0 * im.hi, 2.0 * im.lo};
+    dd2 re = fast_two_sum(s.hi, s.lo + (e1 - e2));
+    // 2 rh ih: (2 rh) ih, and 2 (rh il + rl ih)
+    double q = rh2 * x.ih;
+    double eq = fma(rh2, x.ih, -q);
+    eq = fma(rh2, x.il, eq);
+    eq = fma(x.rl + x.rl, x.ih, eq);
+    dd2 im = fast_two_sum(q, eq);
+    return {re.hi, re.lo, im.hi, im.lo};
 }
 
-// x * w for a complex double-double x and a complex double w
+// x * w for a complex double-double x and a complex double w (last sums as in
+// cdd_sqr)
 __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, double wi) {
     FPE_NO_CONTRACT
     double p1 = x.rh * wr, e1 = fma(x.rh, wr, -p1);
@@ -139,20 +146,21 @@ __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, doubl
     double p2 = x.ih * wi, e2 = fma(x.ih, wi, -p2);
     e2 = fma(x.il, wi, e2);
     dd2 s = two_sum(p1, -p2);
-    dd2 re = two_sum(s.hi, s.lo + (e1 - e2));
+    dd2 re = fast_two_sum(s.hi, s.lo + (e1 - e2));
     double p3 = x.rh * wi, e3 = fma(x.rh, wi, -p3);
     e3 = fma(x.rl, wi, e3);
     double p4 = x.ih * wr, e4 = fma(x.ih, wr, -p4);
     e4 = fma(x.il, wr, e4);
     dd2 t = two_sum(p3, p4);
-    dd2 im = two_sum(t.hi, t.lo + (e3 + e4));
+    dd2 im = fast_two_sum(t.hi, t.lo + (e3 + e4));
     return {re.hi, re.lo, im.hi, im.lo};
 }
 
 // w^n (n >= 0) for |Re w|, |Im w| < 1 with max in [1/2, 1): left-to-right binary
-// powering in double-double, renormalised after every product so that no
-// intermediate leaves the FP64 range.  Returns the rounded mantissa and adds the
-// binary exponent to E.  Relative error about (2 log2 n) 2^-100.
+// powering in double-double, renormalised once per bit (a square times w stays
+// within [1/8, 3) of a renormalised value, far from the FP64 range limits).
+// Returns the rounded mantissa and adds the binary exponent to E.  Relative
+// error about (2 log2 n) 2^-100.
 __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, double &pr, double &pi,
                                         long long &E) {
     if (n == 0) { pr = 1.0; pi = 0.0; return; }
@@ -162,11 +170,8 @@ __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, do
     for (int b = top - 1; b >= 0; --b) {
         x = cdd_sqr(x);
         ex *= 2;                      // squaring doubles the exponent
+        if ((n >> b) & 1) x = cdd_mul_d(x, wr, wi);
         cdd_renorm(x, ex);
-        if ((n >> b) & 1) {
-            x = cdd_mul_d(x, wr, wi);
-            cdd_renorm(x, ex);
-        }
     }
     E += ex;
     pr = x.rh + x.rl;

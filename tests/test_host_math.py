@@ -22,6 +22,11 @@ def hm(tmp_path_factory):
                     "-Wno-unused-command-line-argument", "-o", so, os.path.join(HERE, "host_math.cpp")],
                    check=True, capture_output=True)
     L = ctypes.CDLL(so)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.hm_cdd_sqr.argtypes = [dp, dp]
+    L.hm_cdd_mul_d.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+    L.hm_chunk_start.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                 dp, dp, ctypes.POINTER(ctypes.c_longlong)]
     L.hm_cpow.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_longlong)]
@@ -49,3 +54,67 @@ def test_cpow_dd_against_mpmath(hm):
             assert rel <= 2.0 ** -51, (w, n, float(rel))
             mx = max(abs(pr.value), abs(pi.value))
             assert n == 0 or 0.5 <= mx < 1.0
+
+
+def _normalised_w(rng):
+    t = rng.uniform(0, 2 * np.pi)
+    w = complex(np.cos(t), np.sin(t)) * rng.uniform(0.5, 1.41)
+    k = int(np.floor(np.log2(max(abs(w.real), abs(w.imag))))) + 1
+    return w / 2.0 ** k
+
+
+def _cdd(rng):
+    """A complex double-double with max(|re|, |im|) in [1/2, 1); arguments near
+    +-45 degrees are included (heavy cancellation in Re x^2)."""
+    import mpmath
+    t = rng.uniform(0, 2 * np.pi) if rng.random() < 0.7 else np.pi / 4 * rng.choice([1, 3, 5, 7]) + rng.normal(0, 1e-9)
+    rad = rng.uniform(0.5, 1.41)
+    x = mpmath.mpc(mpmath.cos(t), mpmath.sin(t)) * rad
+    s = max(abs(x.real), abs(x.imag))
+    x = x / mpmath.mpf(2) ** (int(mpmath.floor(mpmath.log(s, 2))) + 1)
+    rh = float(x.real); rl = float(x.real - rh)
+    ih = float(x.imag); il = float(x.imag - ih)
+    return np.array([rh, rl, ih, il])
+
+
+def test_cdd_square_and_product_against_mpmath(hm):
+    """Unrounded double-double results: normwise error <= 2^-100 |result|."""
+    import mpmath
+    mpmath.mp.prec = 300
+    rng = np.random.default_rng(6)
+    out = np.zeros(4)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for _ in range(3000):
+        x = _cdd(rng)
+        xm = mpmath.mpc(mpmath.mpf(x[0]) + mpmath.mpf(x[1]), mpmath.mpf(x[2]) + mpmath.mpf(x[3]))
+        hm.hm_cdd_sqr(x.ctypes.data_as(dp), out.ctypes.data_as(dp))
+        got = mpmath.mpc(mpmath.mpf(out[0]) + mpmath.mpf(out[1]), mpmath.mpf(out[2]) + mpmath.mpf(out[3]))
+        ref = xm * xm
+        assert abs(got - ref) <= 2.0 ** -100 * abs(ref), (x, float(abs(got - ref) / abs(ref)))
+        w = _normalised_w(rng)
+        hm.hm_cdd_mul_d(x.ctypes.data_as(dp), w.real, w.imag, out.ctypes.data_as(dp))
+        got = mpmath.mpc(mpmath.mpf(out[0]) + mpmath.mpf(out[1]), mpmath.mpf(out[2]) + mpmath.mpf(out[3]))
+        ref = xm * mpmath.mpc(w.real, w.imag)
+        assert abs(got - ref) <= 2.0 ** -100 * abs(ref), (x, w, float(abs(got - ref) / abs(ref)))
+
+
+def test_chunk_start_powers_against_mpmath(hm):
+    """w^(c C) from an anchor and chained products: relative error below
+    3 kAnchor 2^-53 (kAnchor = 8), whichever c."""
+    import mpmath
+    mpmath.mp.prec = 256
+    rng = np.random.default_rng(7)
+    pr, pi, E = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+    C = 512
+    worst = 0.0
+    for _ in range(150):
+        w = _normalised_w(rng)
+        for c in [0, 1, 2, 7, 8, 9, 15, 16, 255, 1023, 1953, 2047]:
+            hm.hm_chunk_start(w.real, w.imag, c, C, ctypes.byref(pr), ctypes.byref(pi), ctypes.byref(E))
+            got = mpmath.mpc(pr.value, pi.value) * mpmath.mpf(2) ** E.value
+            exact = mpmath.mpc(w.real, w.imag) ** (c * C)
+            rel = float(abs(got - exact) / abs(exact))
+            worst = max(worst, rel)
+            assert rel <= 3 * 8 * 2.0 ** -53, (w, c, rel)
+            mx = max(abs(pr.value), abs(pi.value))
+            assert c == 0 or 0.5 <= mx < 1.0        # w^0 is returned as 1
