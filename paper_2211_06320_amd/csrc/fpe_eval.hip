@@ -299,16 +299,30 @@ __global__ __launch_bounds__(1024) void k_scan_table(EvalWs W) {
 
 // Counting-sort scatter of the point records, one thread per point: the
 // position is the bin-major prefix of the point's (bin, sort block) entry plus
-// its rank within that entry.  Points of a bin that share a sort block land in
-// an unspecified order; results do not depend on it.
+// its rank within that entry.  Each workgroup first scans the table-scan
+// segment totals in LDS (at most kBins + 1 of them); workgroup 0 also stores
+// them, and their sum, for the later kernels.  Points of a bin that share a
+// sort block land in an unspecified order; results do not depend on it.
 __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
+    __shared__ int32_t s_boff[kSeg];
+    const int nseg = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
+    {
+        int32_t v[4];
+        load4(W.bin_sum, nseg, v);
+        const int32_t tot = block_scan4(v, s_boff, nseg, 0);
+        if (blockIdx.x == 0) {
+            for (int i = threadIdx.x; i < nseg; i += 1024) W.bin_off[i] = s_boff[i];
+            if (threadIdx.x == 0) W.ctl[5] = tot;
+        }
+        __syncthreads();
+    }
     const int j = blockIdx.x * 1024 + threadIdx.x;
     if (j >= n) return;
     const int kr = W.keyrank[j];
     const int key = kr / kSortPoints, rank = kr % kSortPoints;
     if (key == kBins) return;                          // finished points are not sorted
     const int64_t idx = (int64_t)key * W.n_sort_blocks + j / kSortPoints;
-    const int pos = W.tscan[idx] + W.bin_off[key / W.tab_ib] + rank;
+    const int pos = W.tscan[idx] + s_boff[key / W.tab_ib] + rank;
     W.srec[pos] = W.rec[j];
     W.sperm[pos] = j;
 }
@@ -326,15 +340,6 @@ constexpr int kCostUnit = 16;
 constexpr int kPowSteps = 10;
 constexpr int kTileSteps = 8;
 constexpr int kGroupSteps = 64;
-
-// floor(a / b) for 0 <= a < 2^62, 0 < b < 2^31 (quotients here fit in int32):
-// a double quotient, corrected exactly
-__device__ __forceinline__ long long div_floor(long long a, long long b) {
-    long long q = (long long)((double)a / (double)b);
-    while (q * b > a) --q;
-    while ((q + 1) * b <= a) ++q;
-    return q;
-}
 
 struct GroupCost {
     int clo, chi;              // first and last chunk of the group's union window
@@ -378,20 +383,40 @@ __device__ __forceinline__ long long group_total(const GroupCost &gc) {
     return (long long)gc.first + gc.last + (long long)gc.ns * gc.cs + nn * gc.cn;
 }
 
+constexpr int kGroupsPerBlock = 1024 / kWave;
+
+// One wavefront per group of 64 sorted points: the union window, the largest
+// window start and the tile cost; then, per workgroup of kGroupsPerBlock
+// groups, the exclusive prefix of the costs (gcum) and their total (gblk_sum).
 __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
-    const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    if (g >= W.n_groups) return;
-    const int nvalid = valid_points(W);
-    const int idx = g * kWave + lane;
-    int l = INT_MAX, r = INT_MIN;
-    if (idx < nvalid) { const PointRec &rc = W.srec[idx]; l = rc.l; r = rc.r; }
-    const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(idx < nvalid ? l : INT_MIN);
-    if (lane == 0) {
-        W.glo[g] = lo;
-        W.ghi[g] = hi;
-        W.gml[g] = ml;
-        W.gcost[g] = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, P.chunk, W.cost_shift)) : 0;
+    __shared__ int32_t s_cost[kGroupsPerBlock];
+    const int gw = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int g = blockIdx.x * kGroupsPerBlock + gw;
+    int cost = 0;
+    if (g < W.n_groups) {
+        const int nvalid = valid_points(W);
+        const int idx = g * kWave + lane;
+        int l = INT_MAX, r = INT_MIN;
+        if (idx < nvalid) { const PointRec &rc = W.srec[idx]; l = rc.l; r = rc.r; }
+        const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(idx < nvalid ? l : INT_MIN);
+        cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, P.chunk, W.cost_shift)) : 0;
+        if (lane == 0) {
+            W.glo[g] = lo;
+            W.ghi[g] = hi;
+            W.gml[g] = ml;
+            W.gcost[g] = cost;
+        }
+    }
+    if (lane == 0) s_cost[gw] = cost;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int k = 0; k < kGroupsPerBlock; ++k) {
+            const int gg = blockIdx.x * kGroupsPerBlock + k;
+            if (gg < W.n_groups) W.gcum[gg] = acc;
+            acc += s_cost[k];
+        }
+        W.gblk_sum[blockIdx.x] = acc;
     }
 }
 
@@ -399,10 +424,30 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
 // tiles, in (group, chunk) order, cover consecutive intervals of a cost axis of
 // length `total`; wavefront w owns the tiles whose interval starts in
 // [s_w, s_{w+1}), s_w = ceil(w total / NW), so its work is total / NW up to one
-// tile, and the owner of a tile starting at a is floor(a NW / total).
-__device__ __forceinline__ long long group_start(const EvalWs &W, int g) {
-    return (long long)W.gcum[g] + W.gseg_off[g / kSeg];
+// tile, and the owner of a tile starting at a is floor(a NW / total).  A group
+// starts at gcum[g] (its offset inside its k_groups workgroup) plus the
+// exclusive prefix of the workgroup totals: scanned here in LDS when there are
+// at most kPartLds workgroups, otherwise by k_scan_seg and k_scan_sums
+// beforehand.
+
+// floor(a / b) for 0 <= a < 2^62, 0 < b < 2^31 (quotients here fit in int32):
+// a double quotient, corrected exactly
+__device__ __forceinline__ long long div_floor(long long a, long long b) {
+    long long q = (long long)((double)a / (double)b);
+    while (q * b > a) --q;
+    while ((q + 1) * b <= a) ++q;
+    return q;
 }
+
+constexpr int kPartLds = 8192;
+
+struct BlockOffsets {
+    const int32_t *lds;        // exclusive prefix per k_groups workgroup (few workgroups)
+    const int32_t *pre, *seg;  // segment-local prefix and segment offsets (many)
+    __device__ long long at(int b) const {
+        return lds ? (long long)lds[b] : (long long)pre[b] + seg[b / kSeg];
+    }
+};
 
 // the first tile of wavefront w, whose start s lies in group g's interval
 // [A, B) of the cost axis: (g, c) if a tile of g starts exactly at s, else
@@ -430,38 +475,58 @@ __device__ __forceinline__ int2 wave_start(const GroupCost &gc, int g, long long
     return make_int2(g + 1, -1);
 }
 
-// One wavefront per group: the owners of the group's first and last tiles,
-// and the first tile of every window wavefront whose start s_w falls in the
-// group's interval (a group may hold hundreds: the lanes share them out).
-// Wavefront G of the grid sets the wavefronts whose start lies past the end
-// of the work, and the sentinel w = NW, to (G, 0).
-__global__ __launch_bounds__(256) void k_partition(DevPlan P, EvalWs W) {
-    const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int G = (int)W.n_groups, NW = (int)W.n_waves;
-    const long long total = W.ctl[0];
-    if (g > G) return;
-    if (g == G) {
-        // the first wavefront whose start s_w = ceil(w total / NW) reaches total
-        const int wend = total > 0 ? (int)min((long long)NW, div_floor((total - 1) * NW, total) + 1) : 0;
-        for (int w = wend + lane; w <= NW; w += kWave) W.wstart[w] = make_int2(G, 0);
+// threads [0, G): per group, the owners of its first and last tiles; threads
+// [G, G + NW]: per wavefront, its first tile as (group, chunk), or (group, -1)
+// for "the first tile of the first group with tiles at or after this one";
+// (G, 0) past the end of the work and for the sentinel w = NW
+__global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
+    __shared__ int32_t s_off[kPartLds];
+    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = P.chunk;
+    const int nblk = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    BlockOffsets bo{nullptr, W.gblk_pre, W.gseg_off};
+    long long total;
+    if (nblk <= kPartLds) {
+        int32_t carry = 0;
+        for (int s0 = 0; s0 < nblk; s0 += kSeg) {
+            int32_t v[4];
+            load4(W.gblk_sum + s0, min(kSeg, nblk - s0), v);
+            carry += block_scan4(v, s_off + s0, min(kSeg, nblk - s0), carry);
+        }
+        __syncthreads();
+        bo.lds = s_off;
+        total = carry;
+    } else {
+        total = W.ctl[0];
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < G) {
+        const int g = (int)i;
+        const int cost = W.gcost[g];
+        if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
+        const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
+        const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
+        W.gwave[g] = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
         return;
     }
-    const int cost = W.gcost[g];
-    if (cost == 0 || total == 0) {
-        if (lane == 0) W.gwave[g] = make_int2(-1, -1);
-        return;
+    if (i > (int64_t)G + NW) return;
+    const int w = (int)(i - G);
+    const long long sw = total > 0 ? div_floor((long long)w * total + NW - 1, NW) : 0;
+    if (w == NW || total == 0 || sw >= total) { W.wstart[w] = make_int2(G, 0); return; }
+    // the last group starting at or before s_w: first its k_groups workgroup,
+    // then among that workgroup's groups
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bo.at(mid) <= sw) lo = mid; else hi = mid - 1;
     }
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], P.chunk, W.cost_shift);
-    const long long A = group_start(W, g), B = A + cost;
-    if (lane == 0) W.gwave[g] = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
-    // wavefronts with A <= s_w < B
-    const int w0 = A == 0 ? 0 : (int)div_floor((A - 1) * NW, total) + 1;
-    const int w1 = (int)div_floor((B - 1) * NW, total);
-    for (int w = w0 + lane; w <= w1 && w < NW; w += kWave) {
-        const long long sw = div_floor((long long)w * total + NW - 1, NW);
-        W.wstart[w] = wave_start(gc, g, A, B, sw);
-    }
+    const long long base = bo.at(lo);
+    int g = lo * kGroupsPerBlock;
+    const int gend = min(G, g + kGroupsPerBlock);
+    while (g + 1 < gend && base + W.gcum[g + 1] <= sw) ++g;
+    const long long A = base + W.gcum[g], B = A + W.gcost[g];
+    if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
+    W.wstart[w] = wave_start(gc, g, A, B, sw);
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -885,7 +950,8 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     const int64_t NB = (n + kSortPoints - 1) / kSortPoints;
     const int64_t tlen = (int64_t)(kBins + 1) * NB;
     const int tab_ib = NB <= kSeg ? (int)(kSeg / (NB > 0 ? NB : 1)) : 1;
-    const int64_t nseg_t = (kBins + 1 + tab_ib - 1) / tab_ib, nseg_g = (G + kSeg - 1) / kSeg;
+    const int64_t nblk_g = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    const int64_t nseg_t = (kBins + 1 + tab_ib - 1) / tab_ib, nseg_g = (nblk_g + kSeg - 1) / kSeg;
     EvalWs w;
     w.rec = (PointRec *)take(sizeof(PointRec) * n);
     w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
@@ -900,6 +966,8 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     w.ghi = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcost = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcum = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gblk_sum = (int32_t *)take(sizeof(int32_t) * (nblk_g > 0 ? nblk_g : 1));
+    w.gblk_pre = (int32_t *)take(sizeof(int32_t) * (nblk_g > 0 ? nblk_g : 1));
     w.gseg_sum = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
@@ -954,20 +1022,21 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     const int ni = (int)n;
     const unsigned sb = (unsigned)W.n_sort_blocks;
     const unsigned pb = (unsigned)((n + 1023) / 1024);
-    const unsigned gb = (unsigned)((W.n_groups + 15) / 16);
+    const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
 
     FPE_HIP_CHECK(device_setup());
     k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
     if (P.nh > 0) {
         const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
         k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
-        k_scan_sums<<<1, 1024, 0, stream>>>(W.bin_sum, nseg_t, W.bin_off, W.ctl + 5);
         k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
-        k_groups<<<gb, 1024, 0, stream>>>(P, W);
-        const int nseg_g = (int)((W.n_groups + kSeg - 1) / kSeg);
-        k_scan_seg<<<(unsigned)nseg_g, 1024, 0, stream>>>(W.gcost, W.gcum, W.n_groups, W.gseg_sum);
-        k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg_g, W.gseg_off, W.ctl + 0);
-        k_partition<<<(unsigned)((W.n_groups + 1 + 3) / 4), 256, 0, stream>>>(P, W);
+        k_groups<<<(unsigned)nblk_g, 1024, 0, stream>>>(P, W);
+        if (nblk_g > kPartLds) {
+            const int nseg = (nblk_g + kSeg - 1) / kSeg;
+            k_scan_seg<<<(unsigned)nseg, 1024, 0, stream>>>(W.gblk_sum, W.gblk_pre, nblk_g, W.gseg_sum);
+            k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg, W.gseg_off, W.ctl + 0);
+        }
+        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 1023) / 1024), 1024, 0, stream>>>(P, W);
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (g_prof.on) {

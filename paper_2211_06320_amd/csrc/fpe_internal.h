@@ -54,9 +54,10 @@ struct EvalWs {
     int32_t *bin_sum, *bin_off;   // per table-scan segment (tab_ib bins)
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
     int32_t *gml;                 //   largest window start,
-    int32_t *gcost, *gcum;        //   work of its tiles and its segment-local exclusive scan,
+    int32_t *gcost, *gcum;        //   work of its tiles and its prefix within its k_groups workgroup,
     int2 *gwave;                  //   first and last window wavefront owning its tiles
-    int32_t *gseg_sum, *gseg_off; // per 4096-entry segment of the group scan
+    int32_t *gblk_sum, *gblk_pre; // per k_groups workgroup: total work and (many groups) its scan
+    int32_t *gseg_sum, *gseg_off; //   per 4096-entry segment of that scan
     int2 *wstart;                 // per window wavefront: first tile (group, chunk); n_waves + 1
     long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
     int32_t *ctl;                 // [0] total tile work, [5] points in the count table
