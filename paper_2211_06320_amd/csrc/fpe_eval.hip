@@ -60,8 +60,12 @@ constexpr int kSeg = 4096;             // scan segment
 // less than 1 % of lane efficiency against an exact sort by lambda on the
 // uniform and wide-range workloads); |lambda| <= 1106 keeps asinh below 14.6
 __device__ __forceinline__ int lambda_bin(double lam) {
-    double t = asinh(1024.0 * lam) * (1.0 / 34.0) + 0.5;
-    int b = (int)(t * (double)kBins);
+    // asinh in FP32 (the key only orders points; rounding that breaks ties
+    // differently changes which points share a wavefront, not any result)
+    const float x = (float)(1024.0 * lam), ax = fabsf(x);
+    const float a = __logf(ax + __fsqrt_rn(fmaf(ax, ax, 1.0f)));
+    const float t = copysignf(a, x) * (1.0f / 34.0f) + 0.5f;
+    const int b = (int)(t * (float)kBins);
     return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
 }
 
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
     __shared__ double s_s[kHullLds];
     __shared__ int32_t hist[kBins + 1];
     const int t = threadIdx.x, b = blockIdx.x;
-    if (b == 0 && t < 64) W.ctl[t] = 0;               // totals, written by the scans
+    if (b == 0 && t < 64) W.ctl[t] = 0;               // totals and counters of the later kernels
     const bool in_lds = P.nh <= kHullLds;
     if (in_lds)
         for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
@@ -526,7 +530,11 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     const long long A = base + W.gcum[g], B = A + W.gcost[g];
     if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
     const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
-    W.wstart[w] = wave_start(gc, g, A, B, sw);
+    const int2 st = wave_start(gc, g, A, B, sw);
+    W.wstart[w] = st;
+    // w starts inside g and g's first tile belongs to w - 1: g is split, and
+    // w is its second owner (this identifies each split group once)
+    if (st.x == g && div_floor(A * NW, total) == w - 1) W.split[atomicAdd(W.ctl + 8, 1)] = g;
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -823,66 +831,53 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
 
 // Points whose window spans several chunks, in groups split across
 // wavefronts: the sum of the fixed-point partials the owning wavefronts left
-// in their slots.  One workgroup per such group; its threads stride over the
-// owning wavefronts (integer sums: the order does not matter).  The first owner
+// in their slots.  k_partition lists the split groups; workgroups take list
+// entries in turn and stride their threads over the owning wavefronts
+// (integer sums: the order does not matter).  The first owner
 // may hold the group as its last segment (slot 1); every later owner holds it
 // as its first segment (slot 0).
 constexpr int kFinalThreads = 1024;
-constexpr int kFinalUnroll = 1;   // owners' slots in flight per thread
+constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
 
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out, EvalWs W) {
     __shared__ long long part[kFinalThreads / kWave][kWave][4];
-    // a group owned by several wavefronts starts the range of the second one
-    // (inside the group: its first tile belongs to the first owner, its last
-    // tile to a later one), which identifies the group exactly once
-    const int w1 = blockIdx.x + 1;
-    const int g = W.wstart[w1].x;
-    if (W.wstart[w1].y < 0 || g >= W.n_groups) return;
-    const int2 gw = W.gwave[g];
-    if (gw.x != w1 - 1) return;
     const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave, nq = kFinalThreads / kWave;
-    int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
-    resolve_tile(W, P.chunk, fg, fc);
-    const int side0 = fg == g ? 0 : 1;
-    long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    auto slot_of = [&](int w) {
-        return reinterpret_cast<const longlong2 *>(W.slots +
-                                                   ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4);
-    };
-    int w = gw.x + q;
-    for (; w + (kFinalUnroll - 1) * nq <= gw.y; w += kFinalUnroll * nq) {
-        longlong2 x[kFinalUnroll][2];
-#pragma unroll
-        for (int u = 0; u < kFinalUnroll; ++u) {
-            const longlong2 *sl = slot_of(w + u * nq);
-            x[u][0] = sl[0];
-            x[u][1] = sl[1];
+    const int nsplit = W.ctl[8];
+    for (int it = blockIdx.x; it < nsplit; it += gridDim.x) {
+        const int g = W.split[it];
+        const int2 gw = W.gwave[g];
+        int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
+        resolve_tile(W, P.chunk, fg, fc);
+        const int side0 = fg == g ? 0 : 1;
+        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int w = gw.x + q; w <= gw.y; w += nq) {
+            const longlong2 *sl = reinterpret_cast<const longlong2 *>(
+                W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4);
+            const longlong2 x0 = sl[0], x1 = sl[1];
+            a0 += x0.x; a1 += x0.y; a2 += x1.x; a3 += x1.y;
         }
-#pragma unroll
-        for (int u = 0; u < kFinalUnroll; ++u) { a0 += x[u][0].x; a1 += x[u][0].y; a2 += x[u][1].x; a3 += x[u][1].y; }
+        part[q][lane][0] = a0; part[q][lane][1] = a1; part[q][lane][2] = a2; part[q][lane][3] = a3;
+        __syncthreads();
+        if (q == 0) {
+            for (int k = 1; k < nq; ++k) {
+                a0 += part[k][lane][0]; a1 += part[k][lane][1]; a2 += part[k][lane][2]; a3 += part[k][lane][3];
+            }
+            const int p = g * kWave + lane;
+            if (p < valid_points(W)) {
+                const PointRec rc = W.srec[p];
+                if (rc.l / P.chunk != rc.r / P.chunk) {
+                    double2 m;
+                    long long e;
+                    fix_out(P, a0, a1, a2, a3, rc.eref, m, e);
+                    const int j = W.sperm[p];
+                    m_out[j] = m;
+                    e_out[j] = e;
+                }
+            }
+        }
+        __syncthreads();
     }
-    for (; w <= gw.y; w += nq) {
-        const longlong2 *sl = slot_of(w);
-        const longlong2 x0 = sl[0], x1 = sl[1];
-        a0 += x0.x; a1 += x0.y; a2 += x1.x; a3 += x1.y;
-    }
-    part[q][lane][0] = a0; part[q][lane][1] = a1; part[q][lane][2] = a2; part[q][lane][3] = a3;
-    __syncthreads();
-    if (q != 0) return;
-    for (int k = 1; k < nq; ++k) {
-        a0 += part[k][lane][0]; a1 += part[k][lane][1]; a2 += part[k][lane][2]; a3 += part[k][lane][3];
-    }
-    const int p = g * kWave + lane;
-    if (p >= valid_points(W)) return;
-    const PointRec rc = W.srec[p];
-    if (rc.l / P.chunk == rc.r / P.chunk) return;
-    double2 m;
-    long long e;
-    fix_out(P, a0, a1, a2, a3, rc.eref, m, e);
-    const int j = W.sperm[p];
-    m_out[j] = m;
-    e_out[j] = e;
 }
 
 int g_num_cu = 0;
@@ -971,6 +966,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     w.gseg_sum = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
+    w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.n_waves = window_waves();
     w.wstart = (int2 *)take(sizeof(int2) * (w.n_waves + 1));
     w.slots = (long long *)take(sizeof(long long) * 4 * kWave * 2 * w.n_waves);
@@ -1049,7 +1045,8 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
-        if (W.n_waves > 1) k_finalize<<<(unsigned)(W.n_waves - 1), kFinalThreads, 0, stream>>>(P, m, e, W);
+        if (W.n_waves > 1)
+            k_finalize<<<(unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks), kFinalThreads, 0, stream>>>(P, m, e, W);
     }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");
