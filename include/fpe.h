@@ -150,6 +150,36 @@ fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n,
                     double *m_dev, int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
                     void *workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
+/* Q_lambda(z_j) as fpe_eval does, and in the same pass its derivative
+ * Q'_lambda(z_j) = sum over k in G_p within [l_j, r_j] of k a_k z_j^(k-1): the
+ * derivative of the terms the method keeps, through the same window (the
+ * Newton iteration of Section 7.2 divides P by P' evaluated this way).
+ *
+ *   z_dev, n       as fpe_eval.
+ *   m_dev, e_dev   outputs: Q = m 2^e, as fpe_eval.
+ *   md_dev, ed_dev outputs: 2n doubles and n int64, Q' = md 2^ed (same
+ *                  normalisation as m, e).
+ *   workspace_dev  at least fpe_eval_workspace_size bytes (the same workspace
+ *                  serves fpe_eval and fpe_eval_deriv).
+ *
+ * Special points as fpe_eval; where no term of degree >= 1 is kept (z = 0, or
+ * |z| so small that a_0 dominates by more than T bits) Q' = 0, e = 0; a
+ * non-finite z gives NaN.  Errors as fpe_eval. */
+fpe_status fpe_eval_deriv(fpe_plan_t plan, const double *z_dev, int64_t n,
+                          double *m_dev, int64_t *e_dev, double *md_dev, int64_t *ed_dev,
+                          void *workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* One Newton step per point (Section 7.2, eq. newton): z_out = z - Q / Q' with
+ * Q and Q' from fpe_eval_deriv (written to m, e, md, ed as there; the caller
+ * keeps them).  The quotient is taken on the mantissas and scaled by
+ * 2^(e - ed), so it is finite wherever it is representable.  Where Q' = 0 or z
+ * is not finite, z_out is NaN.  z_out_dev: 2n doubles (may alias nothing else).
+ * Errors as fpe_eval. */
+fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n,
+                           double *m_dev, int64_t *e_dev, double *md_dev, int64_t *ed_dev,
+                           double *z_out_dev, void *workspace_dev, size_t workspace_bytes,
+                           hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Same-GPU baseline: Horner's rule on the full polynomial (Section 1).      */
 /* ------------------------------------------------------------------------- */

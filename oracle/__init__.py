@@ -59,6 +59,8 @@ def lib() -> ctypes.CDLL:
     L.ora_plan_scales.argtypes = [ctypes.c_void_p, _i64p]
     L.ora_eval.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int64, _f64p, _i64p, _i64p, _i64p,
                            _i64p, _f64p, _i64p, _f64p, _f64p, ctypes.c_int]
+    L.ora_eval_deriv.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int64, _f64p, _i64p, _f64p, _i64p,
+                                 _f64p, _i64p, _f64p, _i64p, ctypes.c_int]
     L.ora_horner.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
     L.ora_absum.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
     _LIB = L
@@ -163,6 +165,25 @@ class OraclePlan:
                        nthreads or default_threads())
         return {"m": m.view(np.complex128), "e": e, "l": l, "r": r, "terms": t,
                 "dwin_m": dm, "dwin_e": de, "lambda": lam, "N": N}
+
+    def eval_deriv(self, z, nthreads: int | None = None) -> dict:
+        """Q_lambda(z) and Q'_lambda(z) = sum over the kept terms of k a_k z^(k-1),
+        each as (m, e), with their window scales sum |a_k||z|^k and sum |k a_k||z|^(k-1)."""
+        zri = _as_ri(np.atleast_1d(z))
+        n = zri.shape[0] // 2
+        m = np.zeros(2 * n, np.float64)
+        e = np.zeros(n, np.int64)
+        dm = np.zeros(n, np.float64)
+        de = np.zeros(n, np.int64)
+        md = np.zeros(2 * n, np.float64)
+        ed = np.zeros(n, np.int64)
+        ddm = np.zeros(n, np.float64)
+        dde = np.zeros(n, np.int64)
+        lib().ora_eval_deriv(self._h, _ptr(zri, _f64p), n, _ptr(m, _f64p), _ptr(e, _i64p), _ptr(dm, _f64p),
+                             _ptr(de, _i64p), _ptr(md, _f64p), _ptr(ed, _i64p), _ptr(ddm, _f64p),
+                             _ptr(dde, _i64p), nthreads or default_threads())
+        return {"m": m.view(np.complex128), "e": e, "dwin_m": dm, "dwin_e": de,
+                "md": md.view(np.complex128), "ed": ed, "ddwin_m": ddm, "ddwin_e": dde}
 
 
 def precondition(coeffs, p: int = 53, offset: int | None = None) -> OraclePlan:

@@ -389,18 +389,21 @@ static double ora_log2abs(double x, double y)
 /* ------------------------------------------------------------------------- */
 typedef struct {
     double m[2]; int64_t e;     /* Q_lambda(z) = (m0 + i m1) 2^e */
+    double md[2]; int64_t de;   /* Q'_lambda(z) = sum over the kept terms of k a_k z^(k-1) */
+    double ddm; int64_t dde;    /* sum over the window of |k a_k| |z|^(k-1) (its scale) */
     int64_t l, r;               /* window; l > r when empty */
     int64_t terms;              /* #(G_p within [l, r]) */
     double dwin_m; int64_t dwin_e;   /* sum over [l, r] of |a_k||z|^k */
     double lambda, N;
 } ora_res;
 
-static void ora_eval1(const ora_plan *P, double zr, double zi, ora_res *o)
+static void ora_eval1(const ora_plan *P, double zr, double zi, int deriv, ora_res *o)
 {
     memset(o, 0, sizeof *o);
     o->l = 0; o->r = -1;
     if (!isfinite(zr) || !isfinite(zi)) {
         o->m[0] = o->m[1] = NAN; o->lambda = NAN; o->N = NAN;
+        o->md[0] = o->md[1] = NAN;
         return;
     }
     if (P->nh == 0) return;                          /* P == 0 */
@@ -474,6 +477,27 @@ static void ora_eval1(const ora_plan *P, double zr, double zi, ora_res *o)
     xc_out(S, o->m, &o->e);
     o->terms = U;
     o->dwin_m = D.m; o->dwin_e = D.e;
+
+    /* derivative of the kept terms (the same window and good set):
+       Q' = sum of k a_k z^(k-1), with the running power z^(k-1); and its scale
+       sum of |k a_k| |z|^(k-1) over the window */
+    if (deriv) {
+        int64_t k0 = l < 1 ? 1 : l;
+        xc_t pd = xc_pow(z, k0 - 1);
+        xc_t Sd = xc_from(0.0, 0.0);
+        xr_t Dd = { 0.0, 0 };
+        for (int64_t k = k0; k <= r; ++k) {
+            double ar = a[2 * k], ai = a[2 * k + 1];
+            if (ar != 0.0 || ai != 0.0) {
+                double pabs = hypot(pd.re.hi, pd.im.hi);
+                Dd = xr_add(Dd, xr_norm((xr_t){ hypot(ar, ai) * (double)k * pabs, pd.e }));
+            }
+            if (P->good[k]) Sd = xc_add(Sd, xc_mul(xc_mul(xc_from(ar, ai), xc_from((double)k, 0.0)), pd));
+            if (k < r) pd = xc_mul(pd, z);
+        }
+        xc_out(Sd, o->md, &o->de);
+        o->ddm = Dd.m; o->dde = Dd.e;
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -592,6 +616,7 @@ typedef struct {
     const double *z; int64_t i0, i1;
     double *m; int64_t *e, *l, *r, *terms;
     double *dwin_m; int64_t *dwin_e; double *lambda, *N;
+    double *md; int64_t *de; double *ddm; int64_t *dde;   /* derivative (eval only) */
 } ora_job;
 
 static void *ora_worker(void *arg)
@@ -601,8 +626,12 @@ static void *ora_worker(void *arg)
         double zr = J->z[2 * i], zi = J->z[2 * i + 1];
         if (J->kind == 0) {
             ora_res o;
-            ora_eval1(J->P, zr, zi, &o);
+            ora_eval1(J->P, zr, zi, J->md != NULL, &o);
             J->m[2 * i] = o.m[0]; J->m[2 * i + 1] = o.m[1]; J->e[i] = o.e;
+            if (J->md) {
+                J->md[2 * i] = o.md[0]; J->md[2 * i + 1] = o.md[1]; J->de[i] = o.de;
+                J->ddm[i] = o.ddm; J->dde[i] = o.dde;
+            }
             if (J->l) J->l[i] = o.l;
             if (J->r) J->r[i] = o.r;
             if (J->terms) J->terms[i] = o.terms;
@@ -645,20 +674,29 @@ void ora_eval(const ora_plan *P, const double *z, int64_t n, double *m, int64_t 
               int64_t *l, int64_t *r, int64_t *terms, double *dwin_m, int64_t *dwin_e,
               double *lambda, double *N, int nthreads)
 {
-    ora_job J = { 0, P, NULL, 0, z, 0, 0, m, e, l, r, terms, dwin_m, dwin_e, lambda, N };
+    ora_job J = { 0, P, NULL, 0, z, 0, 0, m, e, l, r, terms, dwin_m, dwin_e, lambda, N, NULL, NULL, NULL, NULL };
+    ora_run(J, n, nthreads);
+}
+
+/* Q and Q' (the derivative of the kept terms), with the scale of each */
+void ora_eval_deriv(const ora_plan *P, const double *z, int64_t n, double *m, int64_t *e,
+                    double *dwin_m, int64_t *dwin_e, double *md, int64_t *de, double *ddm, int64_t *dde,
+                    int nthreads)
+{
+    ora_job J = { 0, P, NULL, 0, z, 0, 0, m, e, NULL, NULL, NULL, dwin_m, dwin_e, NULL, NULL, md, de, ddm, dde };
     ora_run(J, n, nthreads);
 }
 
 void ora_horner(const double *coef, int64_t d, const double *z, int64_t n,
                 double *m, int64_t *e, int nthreads)
 {
-    ora_job J = { 1, NULL, coef, d, z, 0, 0, m, e, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
+    ora_job J = { 1, NULL, coef, d, z, 0, 0, m, e, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
     ora_run(J, n, nthreads);
 }
 
 void ora_absum(const double *coef, int64_t d, const double *z, int64_t n,
                double *dm, int64_t *de, int nthreads)
 {
-    ora_job J = { 2, NULL, coef, d, z, 0, 0, dm, de, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
+    ora_job J = { 2, NULL, coef, d, z, 0, 0, dm, de, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
     ora_run(J, n, nthreads);
 }

@@ -71,6 +71,10 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_workspace_size.argtypes = [vp, i64, P(sz)]
     L.fpe_eval.restype = i32
     L.fpe_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_eval_deriv.restype = i32
+    L.fpe_eval_deriv.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_newton_step.restype = i32
+    L.fpe_newton_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_horner_eval.restype = i32
     L.fpe_horner_eval.argtypes = [vp, i64, vp, i64, vp, vp, vp]
     L.fpe_profile_enable.restype = i32
@@ -204,6 +208,37 @@ class Plan:
         if terms or window:
             return m, e, t, w
         return m, e
+
+
+    def eval_deriv(self, z, stream=None):
+        """Q_lambda(z) and its derivative through the same window; returns
+        (m, e, md, ed) with Q = m 2^e and Q' = md 2^ed."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        n = z.shape[0]
+        m = torch.empty(n, dtype=torch.complex128, device=z.device)
+        e = torch.empty(n, dtype=torch.int64, device=z.device)
+        md = torch.empty(n, dtype=torch.complex128, device=z.device)
+        ed = torch.empty(n, dtype=torch.int64, device=z.device)
+        ws, nb = self.workspace(n)
+        _check(lib().fpe_eval_deriv(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
+                                    ed.data_ptr(), ws, nb, _stream(stream)))
+        return m, e, md, ed
+
+    def newton_step(self, z, stream=None):
+        """One Newton step z - Q/Q' per point; returns (z_new, m, e, md, ed)."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        n = z.shape[0]
+        m = torch.empty(n, dtype=torch.complex128, device=z.device)
+        e = torch.empty(n, dtype=torch.int64, device=z.device)
+        md = torch.empty(n, dtype=torch.complex128, device=z.device)
+        ed = torch.empty(n, dtype=torch.int64, device=z.device)
+        zn = torch.empty(n, dtype=torch.complex128, device=z.device)
+        ws, nb = self.workspace(n)
+        _check(lib().fpe_newton_step(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
+                                     ed.data_ptr(), zn.data_ptr(), ws, nb, _stream(stream)))
+        return zn, m, e, md, ed
 
 
 def precondition(coeffs, p: int = 53, stream=None) -> Plan:

@@ -90,7 +90,8 @@ __device__ __forceinline__ int valid_points(const EvalWs &W) {
 // P == 0) get their value here and the bin kBins.  Returns the bin.
 __device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, const double *hs,
                                             const double2 *__restrict__ z, int j, double2 *__restrict__ m_out,
-                                            long long *__restrict__ e_out, int32_t *__restrict__ terms,
+                                            long long *__restrict__ e_out, double2 *__restrict__ md_out,
+                                            long long *__restrict__ ed_out, int32_t *__restrict__ terms,
                                             long long *__restrict__ win, const EvalWs &W) {
     const int nh = P.nh;
     const double2 zz = z[j];
@@ -157,7 +158,13 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, 
         er = (long long)floor(N) + 2;
         key = lambda_bin(lam);
     }
-    if (done) { m_out[j] = mo; e_out[j] = eo; }
+    if (done) {
+        m_out[j] = mo;
+        e_out[j] = eo;
+        // the kept terms of a finished point are at most a_0: derivative 0
+        // (NaN for a non-finite z)
+        if (md_out) { md_out[j] = mo.x != mo.x ? mo : make_double2(0.0, 0.0); ed_out[j] = 0; }
+    }
     if (terms) terms[j] = cnt;
     if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
     PointRec rc;
@@ -176,6 +183,8 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, 
 __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const double2 *__restrict__ z, int n,
                                                            double2 *__restrict__ m_out,
                                                            long long *__restrict__ e_out,
+                                                           double2 *__restrict__ md_out,
+                                                           long long *__restrict__ ed_out,
                                                            int32_t *__restrict__ terms,
                                                            long long *__restrict__ win, EvalWs W) {
     __shared__ double s_k[kHullLds];
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
     for (int it = 0; it < kPerThread; ++it) {
         const int j = b * kSortPoints + it * kBoundsThreads + t;
         if (j < n) {
-            const int key = bounds_point(P, hk, hs, z, j, m_out, e_out, terms, win, W);
+            const int key = bounds_point(P, hk, hs, z, j, m_out, e_out, md_out, ed_out, terms, win, W);
             const int rank = atomicAdd(&hist[key], 1);  // LDS
             W.keyrank[j] = key * kSortPoints + rank;
         }
@@ -571,25 +580,41 @@ __device__ __forceinline__ void load_batch(double *dst, const_table_t p) {
 // s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima)
 __device__ __forceinline__ void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
+// The running Horner value of a lane, and with D its derivative in z:
+//   H' <- H' z + H (the old H), then H <- H z + a_k
+template <bool D> struct Acc { double hr = 0.0, hi = 0.0; };
+template <> struct Acc<true> { double hr = 0.0, hi = 0.0, dr = 0.0, di = 0.0; };
+
+template <bool D>
+__device__ __forceinline__ void acc_step(Acc<D> &a, double zr, double zi, double ar, double ai) {
+    if constexpr (D) {
+        FPE_NO_CONTRACT
+        const double tr = fma(-a.di, zi, a.hr), ti = fma(a.dr, zi, a.hi);
+        a.dr = fma(a.dr, zr, tr);
+        a.di = fma(a.di, zr, ti);
+    }
+    horner_step(a.hr, a.hi, zr, zi, ar, ai);
+}
+
 // Which lanes take the step of coefficient k in a tile where lane i covers
 // [lo_i, hi_i]: all of them (the common part), those that have started
 // (k <= hi_i, the ragged top), those that have not finished (k >= lo_i, the
 // ragged bottom), or both tests.
 enum StepMask { kAll = 0, kTop = 1, kBottom = 2, kBoth = 3 };
 
-template <int M>
-__device__ __forceinline__ void masked_step(double &hr, double &hi_, double zr, double zi, double ar, double ai,
-                                            int k, int lo, int hi) {
+template <int M, bool D>
+__device__ __forceinline__ void masked_step(Acc<D> &a, double zr, double zi, double ar, double ai, int k, int lo,
+                                            int hi) {
     if ((M & kTop) && k > hi) return;
     if ((M & kBottom) && k < lo) return;
-    horner_step(hr, hi_, zr, zi, ar, ai);
+    acc_step(a, zr, zi, ar, ai);
 }
 
-template <int M>
-__device__ __forceinline__ void batch_steps(double &hr, double &hi_, double zr, double zi, const double *X, int kbase,
-                                            int lo, int hi) {
+template <int M, bool D>
+__device__ __forceinline__ void batch_steps(Acc<D> &a, double zr, double zi, const double *X, int kbase, int lo,
+                                            int hi) {
 #pragma unroll
-    for (int s2 = kBatch - 1; s2 >= 0; --s2) masked_step<M>(hr, hi_, zr, zi, X[2 * s2], X[2 * s2 + 1], kbase + s2, lo, hi);
+    for (int s2 = kBatch - 1; s2 >= 0; --s2) masked_step<M>(a, zr, zi, X[2 * s2], X[2 * s2 + 1], kbase + s2, lo, hi);
 }
 
 // Horner steps for k = kfrom, kfrom - 1, ..., kto (none if kfrom < kto); kfrom
@@ -599,9 +624,9 @@ __device__ __forceinline__ void batch_steps(double &hr, double &hi_, double zr, 
 // an unconditional wait for itself (nothing else is in flight then), requests
 // the next batch, and runs its steps, which need no further wait even when
 // they are masked.
-template <int M>
-__device__ __forceinline__ void run_steps(double &hr, double &hi_, double zr, double zi, const_table_t cf,
-                                          int kfrom, int kto, int lo, int hi) {
+template <int M, bool D>
+__device__ __forceinline__ void run_steps(Acc<D> &a, double zr, double zi, const_table_t cf, int kfrom, int kto,
+                                          int lo, int hi) {
     if (kfrom < kto) return;
     const int nb = (kfrom - kto + 1) / kBatch;
     int k = kfrom;
@@ -617,24 +642,34 @@ __device__ __forceinline__ void run_steps(double &hr, double &hi_, double zr, do
             __builtin_amdgcn_sched_barrier(0);
             load_batch(B, base - 2 * kBatch * (bi + 1));
             __builtin_amdgcn_sched_barrier(0);
-            batch_steps<M>(hr, hi_, zr, zi, A, kb0 - kBatch * bi, lo, hi);
+            batch_steps<M>(a, zr, zi, A, kb0 - kBatch * bi, lo, hi);
             wait_scalar_loads();
             __builtin_amdgcn_sched_barrier(0);
             if (bi + 2 < nb) load_batch(A, base - 2 * kBatch * (bi + 2));
             __builtin_amdgcn_sched_barrier(0);
-            batch_steps<M>(hr, hi_, zr, zi, B, kb0 - kBatch * (bi + 1), lo, hi);
+            batch_steps<M>(a, zr, zi, B, kb0 - kBatch * (bi + 1), lo, hi);
         }
         if (bi < nb) {
             wait_scalar_loads();
-            batch_steps<M>(hr, hi_, zr, zi, A, kb0 - kBatch * bi, lo, hi);
+            batch_steps<M>(a, zr, zi, A, kb0 - kBatch * bi, lo, hi);
         }
         k -= kBatch * nb;
     }
-    for (; k >= kto; --k) masked_step<M>(hr, hi_, zr, zi, cf[2 * k], cf[2 * k + 1], k, lo, hi);
+    for (; k >= kto; --k) masked_step<M>(a, zr, zi, cf[2 * k], cf[2 * k + 1], k, lo, hi);
 }
 
 constexpr int kWindowThreads = 256;
 constexpr int kWindowWaves = kWindowThreads / kWave;
+
+// fixed-point words per lane and window-wavefront slot: the sums of Q, then of Q'
+constexpr int kSlotWords = 8;
+
+// reference exponent of the derivative's terms k a_k z^(k-1): each is below
+// r 2^(N - lambda), and with lambda >= ez - 1 (z = w 2^ez) and eref = floor(N) + 2,
+// eref + 1 - ez + bitlen(r) bounds floor(N - lambda) + 2 + bitlen(r) from above
+__device__ __forceinline__ long long deriv_eref(long long eref, int ez, int r) {
+    return eref + 1 - ez + (32 - __clz(r > 0 ? r : 1));
+}
 
 // fixed-point form of a partial value (qr + i qi) 2^E relative to 2^eref: a
 // high word (integer part of value 2^(fix_shift - eref)) and a low word
@@ -659,15 +694,21 @@ __device__ __forceinline__ void fix_out(const DevPlan &P, long long a0, long lon
     normalise(vr, vi, eref, m, e);
 }
 
+// With D, the same pass also sums the derivative of the kept terms,
+// Q'(z) = sum k a_k z^(k-1) over G_p within [l, r], into (md_out, ed_out).
+template <bool D>
 __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *__restrict__ m_out,
-                                                           long long *__restrict__ e_out, EvalWs W) {
+                                                           long long *__restrict__ e_out,
+                                                           double2 *__restrict__ md_out,
+                                                           long long *__restrict__ ed_out, EvalWs W) {
+    constexpr int kAccWords = D ? 8 : 4;
     const int lane = threadIdx.x % kWave;
     const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
     // per lane: the chained w^(c C) and w^C, and the fixed-point sums of the
     // segment (kept here, not in registers: they are touched once per tile)
     __shared__ double s_ch[4][kWindowThreads];
     __shared__ long long s_che[2][kWindowThreads];
-    __shared__ long long s_acc[4][kWindowThreads];    // fixed-point sums of the segment
+    __shared__ long long s_acc[kAccWords][kWindowThreads];   // fixed-point sums of the segment
     if (w >= W.n_waves) return;
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
@@ -689,8 +730,8 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
     // lie inside a split group's owner range, where the finalize kernel reads
     // its slot 0; every other slot that kernel reads is written below
     if (g == ge && c == ce) {
-        long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * 4;
-        s0[0] = 0; s0[1] = 0; s0[2] = 0; s0[3] = 0;
+        long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * kSlotWords;
+        for (int k = 0; k < kAccWords; ++k) s0[k] = 0;
     }
     bool first_segment = true;
     // one pass per group segment: the consecutive tiles of one group this
@@ -716,7 +757,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
         int chain_c = -1;                                 // chunk of the chained power; -1: none
         bool have_zc = false;
         bool xv = false;                                  // this lane's chained power is w^(chain_c C)
-        s_acc[0][threadIdx.x] = 0; s_acc[1][threadIdx.x] = 0; s_acc[2][threadIdx.x] = 0; s_acc[3][threadIdx.x] = 0;
+        for (int k = 0; k < kAccWords; ++k) s_acc[k][threadIdx.x] = 0;
         for (;;) {
             // ---- tile (g, c): this lane's part [lo, hi] of chunk c
             const int c0 = c * C, c1 = c0 + C - 1;
@@ -775,20 +816,31 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
                     xv = cont;
                     chain_c = c;
                 }
-                double hr = 0.0, hi_ = 0.0;
+                Acc<D> acc;
                 const double zr = ldexp(wr, ez), zi = ldexp(wi, ez);
                 if (Ahi >= Alo) {
-                    run_steps<kTop>(hr, hi_, zr, zi, cf, Khi, Ahi + 1, lo, hi);
-                    run_steps<kAll>(hr, hi_, zr, zi, cf, Ahi, Alo, lo, hi);
-                    run_steps<kBottom>(hr, hi_, zr, zi, cf, Alo - 1, Klo, lo, hi);
+                    run_steps<kTop>(acc, zr, zi, cf, Khi, Ahi + 1, lo, hi);
+                    run_steps<kAll>(acc, zr, zi, cf, Ahi, Alo, lo, hi);
+                    run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
                 } else {
-                    run_steps<kBoth>(hr, hi_, zr, zi, cf, Khi, Klo, lo, hi);
+                    run_steps<kBoth>(acc, zr, zi, cf, Khi, Klo, lo, hi);
                 }
                 if (act) {
                     // times z^lo = (pr + i pi) 2^(pe + lo ez)
                     const long long E = P.coef_shift + pe + (long long)lo * ez;
-                    const double qr = fma(hr, pr, -hi_ * pi);
-                    const double qi = fma(hr, pi, hi_ * pr);
+                    const double qr = fma(acc.hr, pr, -acc.hi * pi);
+                    const double qi = fma(acc.hr, pi, acc.hi * pr);
+                    double dqr = 0.0, dqi = 0.0;
+                    if constexpr (D) {
+                        // d/dz (z^lo H) = z^lo (lo H + z H') / z, and 1/z = conj(w) / |w|^2 2^-ez
+                        FPE_NO_CONTRACT
+                        const double ur = fma((double)lo, acc.hr, fma(zr, acc.dr, -zi * acc.di));
+                        const double ui = fma((double)lo, acc.hi, fma(zr, acc.di, zi * acc.dr));
+                        const double inv = 1.0 / fma(wr, wr, wi * wi);
+                        const double vr = fma(ur, wr, ui * wi) * inv, vi = fma(ui, wr, -ur * wi) * inv;
+                        dqr = fma(vr, pr, -vi * pi);
+                        dqi = fma(vr, pi, vi * pr);
+                    }
                     if (!multi) {
                         double2 m;
                         long long e;
@@ -796,8 +848,17 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
                         const int j = W.sperm[idx];
                         m_out[j] = m;
                         e_out[j] = e;
+                        if constexpr (D) {
+                            normalise(dqr, dqi, E - ez, m, e);
+                            md_out[j] = m;
+                            ed_out[j] = e;
+                        }
                     } else {
-                        fix_add(P, qr, qi, E, W.srec[idx].eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
+                        const long long eref = W.srec[idx].eref;
+                        fix_add(P, qr, qi, E, eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
+                        if constexpr (D)
+                            fix_add(P, dqr, dqi, E - ez, deriv_eref(eref, ez, r), s_acc[4][t], s_acc[5][t],
+                                    s_acc[6][t], s_acc[7][t]);
                     }
                 }
             }
@@ -810,17 +871,22 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
         // (0: its first segment, 1: its last)
         if (multi) {
             const int t = threadIdx.x;
-            const long long a0 = s_acc[0][t], a1 = s_acc[1][t], a2 = s_acc[2][t], a3 = s_acc[3][t];
             if (seg_c0 == clo && c == chi) {
                 double2 m;
                 long long e;
-                fix_out(P, a0, a1, a2, a3, W.srec[idx].eref, m, e);
+                const long long eref = W.srec[idx].eref;
+                fix_out(P, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t], eref, m, e);
                 const int j = W.sperm[idx];
                 m_out[j] = m;
                 e_out[j] = e;
+                if constexpr (D) {
+                    fix_out(P, s_acc[4][t], s_acc[5][t], s_acc[6][t], s_acc[7][t], deriv_eref(eref, ez, r), m, e);
+                    md_out[j] = m;
+                    ed_out[j] = e;
+                }
             } else {
-                long long *slot = W.slots + ((size_t)(2 * w + (first_segment ? 0 : 1)) * kWave + lane) * 4;
-                slot[0] = a0; slot[1] = a1; slot[2] = a2; slot[3] = a3;
+                long long *slot = W.slots + ((size_t)(2 * w + (first_segment ? 0 : 1)) * kWave + lane) * kSlotWords;
+                for (int k = 0; k < kAccWords; ++k) slot[k] = s_acc[k][t];
             }
         }
         first_segment = false;
@@ -839,9 +905,13 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
 constexpr int kFinalThreads = 1024;
 constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
 
+template <bool D>
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
-                                                            long long *__restrict__ e_out, EvalWs W) {
-    __shared__ long long part[kFinalThreads / kWave][kWave][4];
+                                                            long long *__restrict__ e_out,
+                                                            double2 *__restrict__ md_out,
+                                                            long long *__restrict__ ed_out, EvalWs W) {
+    constexpr int kAccWords = D ? 8 : 4;
+    __shared__ long long part[kFinalThreads / kWave][kWave][kAccWords];
     const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave, nq = kFinalThreads / kWave;
     const int nsplit = W.ctl[8];
     for (int it = blockIdx.x; it < nsplit; it += gridDim.x) {
@@ -850,29 +920,40 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
         int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
         resolve_tile(W, P.chunk, fg, fc);
         const int side0 = fg == g ? 0 : 1;
-        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        long long a[kAccWords] = {};
         for (int w = gw.x + q; w <= gw.y; w += nq) {
             const longlong2 *sl = reinterpret_cast<const longlong2 *>(
-                W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * 4);
-            const longlong2 x0 = sl[0], x1 = sl[1];
-            a0 += x0.x; a1 += x0.y; a2 += x1.x; a3 += x1.y;
+                W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * kSlotWords);
+#pragma unroll
+            for (int k = 0; k < kAccWords / 2; ++k) {
+                const longlong2 x = sl[k];
+                a[2 * k] += x.x;
+                a[2 * k + 1] += x.y;
+            }
         }
-        part[q][lane][0] = a0; part[q][lane][1] = a1; part[q][lane][2] = a2; part[q][lane][3] = a3;
+#pragma unroll
+        for (int k = 0; k < kAccWords; ++k) part[q][lane][k] = a[k];
         __syncthreads();
         if (q == 0) {
-            for (int k = 1; k < nq; ++k) {
-                a0 += part[k][lane][0]; a1 += part[k][lane][1]; a2 += part[k][lane][2]; a3 += part[k][lane][3];
-            }
+            for (int qq = 1; qq < nq; ++qq)
+#pragma unroll
+                for (int k = 0; k < kAccWords; ++k) a[k] += part[qq][lane][k];
             const int p = g * kWave + lane;
             if (p < valid_points(W)) {
                 const PointRec rc = W.srec[p];
                 if (rc.l / P.chunk != rc.r / P.chunk) {
                     double2 m;
                     long long e;
-                    fix_out(P, a0, a1, a2, a3, rc.eref, m, e);
+                    fix_out(P, a[0], a[1], a[2], a[3], rc.eref, m, e);
                     const int j = W.sperm[p];
                     m_out[j] = m;
                     e_out[j] = e;
+                    if constexpr (D) {
+                        const int ez = exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y)));
+                        fix_out(P, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
+                        md_out[j] = m;
+                        ed_out[j] = e;
+                    }
                 }
             }
         }
@@ -881,14 +962,14 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
 }
 
 int g_num_cu = 0;
-int g_window_blocks_per_cu = 0;
+int g_window_blocks_per_cu[2] = {0, 0};   // without and with the derivative
 
 // wavefronts of the window kernel: as many as are resident at once on the
 // device (the partition hands each one an equal share, so none may wait for a
 // second round)
-int64_t window_waves() {
-    return (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (g_window_blocks_per_cu > 0 ? g_window_blocks_per_cu : 1) *
-           kWindowWaves;
+int64_t window_waves(bool deriv) {
+    const int b = g_window_blocks_per_cu[deriv ? 1 : 0];
+    return (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (b > 0 ? b : 1) * kWindowWaves;
 }
 
 // instrumentation: event pairs around k_window
@@ -907,16 +988,40 @@ hipError_t prof_event(hipEvent_t *ev) {
 // compute units and resident window workgroups per compute unit (once per process)
 hipError_t device_setup() {
     if (g_num_cu > 0) return hipSuccess;
-    int dev = 0, ncu = 0, nb = 0;
+    int dev = 0, ncu = 0, nb0 = 0, nb1 = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_window),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, reinterpret_cast<const void *>(k_window<false>),
+                                                        kWindowThreads, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, reinterpret_cast<const void *>(k_window<true>),
                                                         kWindowThreads, 0);
     if (e != hipSuccess) return e;
-    g_window_blocks_per_cu = nb > 0 ? nb : 1;
+    g_window_blocks_per_cu[0] = nb0 > 0 ? nb0 : 1;
+    g_window_blocks_per_cu[1] = nb1 > 0 ? nb1 : 1;
     g_num_cu = ncu > 0 ? ncu : 256;
     return hipSuccess;
+}
+
+// One Newton step per point, z - Q / Q' with Q = m 2^e and Q' = md 2^ed: the
+// mantissa quotient times 2^(e - ed); Q' = 0 or a non-finite input gives NaN.
+__global__ __launch_bounds__(256) void k_newton(const double2 *__restrict__ z, int n, const double2 *__restrict__ m,
+                                                const long long *__restrict__ e, const double2 *__restrict__ md,
+                                                const long long *__restrict__ ed, double2 *__restrict__ z_out) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double2 zz = z[j], a = m[j], b = md[j];
+    const double den = fma(b.x, b.x, b.y * b.y);
+    if (!(den > 0.0) || !isfinite(zz.x) || !isfinite(zz.y) || a.x != a.x) {
+        z_out[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
+        return;
+    }
+    long long sh = e[j] - ed[j];
+    sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
+    const double qr = ldexp(fma(a.x, b.x, a.y * b.y) / den, (int)sh);
+    const double qi = ldexp(fma(a.y, b.x, -a.x * b.y) / den, (int)sh);
+    z_out[j] = make_double2(zz.x - qr, zz.y - qi);
 }
 
 }  // namespace
@@ -937,7 +1042,7 @@ int cost_shift_for(const DevPlan &P, int64_t n) {
     return -1;
 }
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base) {
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, bool deriv) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
@@ -967,9 +1072,11 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base)
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
     w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
-    w.n_waves = window_waves();
-    w.wstart = (int2 *)take(sizeof(int2) * (w.n_waves + 1));
-    w.slots = (long long *)take(sizeof(long long) * 4 * kWave * 2 * w.n_waves);
+    // one workspace serves both window variants
+    const int64_t nw_max = std::max(window_waves(false), window_waves(true));
+    w.n_waves = window_waves(deriv);
+    w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
+    w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
     w.tab_ib = tab_ib;
@@ -989,31 +1096,35 @@ extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t
     if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
     if (cost_shift_for(plan->dev, n) < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
     FPE_HIP_CHECK(device_setup());
-    *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr);
+    *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, false);
     set_error("");
     return FPE_OK;
 }
 
-extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev,
-                               int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
-                               void *workspace_dev, size_t workspace_bytes, hipStream_t stream) {
+static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
+                            double *md_dev, int64_t *ed_dev, int32_t *terms_dev, int64_t *window_dev,
+                            void *workspace_dev, size_t workspace_bytes, hipStream_t stream) {
+    const bool deriv = md_dev != nullptr;
     if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
     size_t need = 0;
     fpe_status st = fpe_eval_workspace_size(plan, n, &need);
     if (st != FPE_OK) return st;
     if (n == 0) { set_error(""); return FPE_OK; }
-    if (!z_dev || !m_dev || !e_dev || !workspace_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (!z_dev || !m_dev || !e_dev || !workspace_dev || (deriv && !ed_dev))
+        return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     if (workspace_bytes < need)
         return fail(FPE_ERR_WORKSPACE, "eval workspace too small: need " + std::to_string(need));
     if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0 || reinterpret_cast<uintptr_t>(z_dev) % 16 != 0 ||
-        reinterpret_cast<uintptr_t>(m_dev) % 16 != 0)
+        reinterpret_cast<uintptr_t>(m_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(plan->dev, n, &W, workspace_dev);
+    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv);
     const DevPlan &P = plan->dev;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
     double2 *m = reinterpret_cast<double2 *>(m_dev);
     long long *e = reinterpret_cast<long long *>(e_dev);
+    double2 *md = reinterpret_cast<double2 *>(md_dev);
+    long long *ed = reinterpret_cast<long long *>(ed_dev);
     long long *win = reinterpret_cast<long long *>(window_dev);
     const int ni = (int)n;
     const unsigned sb = (unsigned)W.n_sort_blocks;
@@ -1021,7 +1132,7 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
     const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
 
     FPE_HIP_CHECK(device_setup());
-    k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, terms_dev, win, W);
+    k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, md, ed, terms_dev, win, W);
     if (P.nh > 0) {
         const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
         k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
@@ -1040,17 +1151,36 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
             FPE_HIP_CHECK(prof_event(&ev1));
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
-        k_window<<<wb, kWindowThreads, 0, stream>>>(P, m, e, W);
+        if (deriv) k_window<true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, md, ed, W);
+        else k_window<false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         if (g_prof.on) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
-        if (W.n_waves > 1)
-            k_finalize<<<(unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks), kFinalThreads, 0, stream>>>(P, m, e, W);
+        if (W.n_waves > 1) {
+            const unsigned fb = (unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks);
+            if (deriv) k_finalize<true><<<fb, kFinalThreads, 0, stream>>>(P, m, e, md, ed, W);
+            else k_finalize<false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        }
     }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");
     return FPE_OK;
+}
+
+extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
+                               int32_t *terms_dev, int64_t *window_dev, void *workspace_dev, size_t workspace_bytes,
+                               hipStream_t stream) {
+    return eval_impl(plan, z_dev, n, m_dev, e_dev, nullptr, nullptr, terms_dev, window_dev, workspace_dev,
+                     workspace_bytes, stream);
+}
+
+extern "C" fpe_status fpe_eval_deriv(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev,
+                                     int64_t *e_dev, double *md_dev, int64_t *ed_dev, void *workspace_dev,
+                                     size_t workspace_bytes, hipStream_t stream) {
+    if (!md_dev || !ed_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    return eval_impl(plan, z_dev, n, m_dev, e_dev, md_dev, ed_dev, nullptr, nullptr, workspace_dev,
+                     workspace_bytes, stream);
 }
 
 extern "C" fpe_status fpe_profile_enable(int32_t on) {
@@ -1074,6 +1204,23 @@ extern "C" fpe_status fpe_profile_read(double *window_ms, int64_t *launches) {
     g_prof.pending.clear();
     if (window_ms) *window_ms = tot;
     if (launches) *launches = cnt;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev,
+                                      int64_t *e_dev, double *md_dev, int64_t *ed_dev, double *z_out_dev,
+                                      void *workspace_dev, size_t workspace_bytes, hipStream_t stream) {
+    if (!z_out_dev && n > 0) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(z_out_dev) % 16 != 0) return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
+    fpe_status st = fpe_eval_deriv(plan, z_dev, n, m_dev, e_dev, md_dev, ed_dev, workspace_dev, workspace_bytes,
+                                   stream);
+    if (st != FPE_OK || n == 0) return st;
+    k_newton<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
+        reinterpret_cast<const double2 *>(z_dev), (int)n, reinterpret_cast<const double2 *>(m_dev),
+        reinterpret_cast<const long long *>(e_dev), reinterpret_cast<const double2 *>(md_dev),
+        reinterpret_cast<const long long *>(ed_dev), reinterpret_cast<double2 *>(z_out_dev));
+    FPE_HIP_CHECK(hipGetLastError());
     set_error("");
     return FPE_OK;
 }

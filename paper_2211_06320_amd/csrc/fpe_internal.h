@@ -67,7 +67,7 @@ struct EvalWs {
     int32_t tab_ib;               // bins per table-scan segment
 };
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base);
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, bool deriv);
 
 // Read-only tables are read through the constant address space in device code:
 // a wave-uniform index then becomes a scalar load, one per wavefront, broadcast

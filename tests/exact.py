@@ -109,3 +109,19 @@ def cover_vertices(Ehat: dict[int, Fr]):
             verts.append(k)
     verts.append(ks[-1])
     return verts
+
+
+def exact_deriv_subset(coeffs, z, ks):
+    """sum over k in ks (k >= 1) of k a_k z^(k-1) exactly."""
+    zr = (Fr(float(z.real)), Fr(float(z.imag)))
+    tot = (Fr(0), Fr(0))
+    for k in ks:
+        if k == 0:
+            continue
+        p = (Fr(1), Fr(0))
+        for _ in range(k - 1):
+            p = cplx_mul(p, zr)
+        a = coeffs[k]
+        t = cplx_mul((Fr(float(a.real)) * k, Fr(float(a.imag)) * k), p)
+        tot = (tot[0] + t[0], tot[1] + t[1])
+    return tot

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from exact import (concave_majorant, cover_vertices, exact_poly, exact_scale,
+from exact import (concave_majorant, cover_vertices, cplx_mul, exact_deriv_subset, exact_poly, exact_scale,
                    exact_sum_subset, frac_abs_log2, to_complex)
 from paper_2211_06320_amd import workloads
 
@@ -552,3 +552,72 @@ def test_huge_exponents_no_overflow():
             got = mpmath.mpc(m.real, m.imag) * mpmath.mpf(2) ** int(e)
             assert abs(got - ex) / D < 2.0 ** -50
     assert he.max() > 1024   # beyond FP64
+
+
+def test_derivative_exact_rational_tiny():
+    """Q' (the derivative of the kept terms) against exact rationals over the same
+    window and good set, and its scale sum |k a_k||z|^(k-1) against a float sum."""
+    rng = np.random.default_rng(91)
+    for c in _random_tiny_polys(rng, 25):
+        z = _tiny_points(rng, 10)
+        P = oracle.precondition(c, 53)
+        r = P.eval(z)
+        rd = P.eval_deriv(z)
+        assert np.array_equal(rd["m"], r["m"]) and np.array_equal(rd["e"], r["e"])
+        good = P.good()
+        for i, zi in enumerate(z):
+            ks = [k for k in range(r["l"][i], r["r"][i] + 1) if good[k] and k >= 1]
+            terms = [(k, abs(c[k]) * k * abs(zi) ** (k - 1)) for k in range(max(r["l"][i], 1), r["r"][i] + 1)
+                     if c[k] != 0]
+            if not terms:
+                assert rd["md"][i] == 0
+                continue
+            logs = [math.log2(t) for _, t in terms if t > 0]
+            top = max(logs)
+            sh = -int(math.floor(top))
+            Dd = sum(2.0 ** (x - top) for x in logs) * 2.0 ** (top + sh)
+            ex = to_complex(exact_deriv_subset(c, zi, ks), sh)
+            got = math.ldexp(rd["md"][i].real, int(rd["ed"][i]) + sh) + 1j * math.ldexp(rd["md"][i].imag, int(rd["ed"][i]) + sh)
+            assert abs(got - ex) <= 2.0 ** -52 * abs(ex) + 2.0 ** -90 * Dd, (c, zi)
+            gotD = math.ldexp(rd["ddwin_m"][i], int(rd["ddwin_e"][i]) + sh)
+            assert abs(gotD - Dd) <= 1e-12 * Dd
+
+
+def test_derivative_geometric_series_closed_form():
+    """a_k = 1: where the window keeps every term, Q' = P' =
+    (d z^(d+1) - (d+1) z^d + 1) / (z - 1)^2, compared in exact rationals."""
+    rng = np.random.default_rng(92)
+    for d in (5, 17, 40):
+        c = np.ones(d + 1, np.complex128)
+        P = oracle.precondition(c, 53)
+        zs = 2.0 ** rng.uniform(-0.05, 0.05, 8) * np.exp(1j * rng.uniform(0.3, 6.0, 8))
+        rd = P.eval_deriv(zs)
+        for i, zi in enumerate(zs):
+            z = (Fr(float(zi.real)), Fr(float(zi.imag)))
+            zd = (Fr(1), Fr(0))
+            for _ in range(d):
+                zd = cplx_mul(zd, z)                   # z^d
+            zd1 = cplx_mul(zd, z)
+            num = (d * zd1[0] - (d + 1) * zd[0] + 1, d * zd1[1] - (d + 1) * zd[1])
+            zm1 = (z[0] - 1, z[1])
+            den = cplx_mul(zm1, zm1)
+            q = den[0] ** 2 + den[1] ** 2
+            ex = ((num[0] * den[0] + num[1] * den[1]) / q, (num[1] * den[0] - num[0] * den[1]) / q)
+            exc = to_complex(ex)
+            got = rd["md"][i] * 2.0 ** rd["ed"][i]
+            assert abs(got - exc) <= 2.0 ** -50 * d * d, (d, zi, got, exc)
+
+
+def test_newton_step_paper_example():
+    """P = z^64 + 1 at z = 10 (Section 7.2): the window keeps only z^64 (a_0 lies
+    more than T bits below), so Q'/Q gives the step z / 64: 10 - N(10) = 0.15625."""
+    c = np.zeros(65, np.complex128)
+    c[0] = 1.0
+    c[64] = 1.0
+    P = oracle.precondition(c, 53)
+    rd = P.eval_deriv(np.array([10.0 + 0j]))
+    q = rd["m"][0] * 2.0 ** rd["e"][0]
+    qd = rd["md"][0] * 2.0 ** rd["ed"][0]
+    assert q == 10.0 ** 64 and qd == 64 * 10.0 ** 63
+    step = (rd["m"][0] / rd["md"][0]) * 2.0 ** (int(rd["e"][0]) - int(rd["ed"][0]))
+    assert 10.0 - (10.0 - step) == 0.15625
