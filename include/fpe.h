@@ -180,6 +180,36 @@ fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n,
                            double *z_out_dev, void *workspace_dev, size_t workspace_bytes,
                            hipStream_t stream);
 
+/* Reverse mode of the map (a, z) -> Q_lambda(z) at n points, for upstream
+ * gradients g_j (eq. reducedQlambda; the kept set G_p within [l_j, r_j] is
+ * held fixed, as the map is piecewise polynomial in a and z).  The convention
+ * is that of complex reverse-mode differentiation (PyTorch's): the gradient of
+ * a holomorphic map is the upstream gradient times the conjugate of its
+ * derivative, so
+ *   grad_a[k] = sum over the points j whose kept terms include k of g_j conj(z_j)^k,
+ *   grad_z[j] = g_j conj(Q'_lambda(z_j)).
+ *
+ *   z_dev, n         as fpe_eval.
+ *   g_dev            2n doubles: the upstream gradients, input order.
+ *   md_dev, ed_dev   Q' = md 2^ed from fpe_eval_deriv at the same points (only
+ *                    read when grad_z_dev is not NULL).
+ *   grad_a_dev       output, or NULL to skip: 2 (d + 1) doubles, overwritten
+ *                    (zero outside G_p and where no window reaches k).
+ *   grad_z_dev       output, or NULL to skip: 2n doubles.
+ *   workspace_dev    at least fpe_eval_workspace_size bytes (the workspace of
+ *                    fpe_eval serves).
+ *
+ * Both gradients are plain doubles: a term beyond the double range saturates
+ * to an infinity (or NaN where an infinity meets a zero), and one below it
+ * flushes to zero.  A point with a non-finite coordinate contributes nothing
+ * to grad_a and gets a NaN grad_z; z = 0 contributes g_j to grad_a[0] when
+ * a_0 != 0.  grad_a sums the points' terms with FP64 atomic additions, so its
+ * last bits can vary from call to call.  Errors as fpe_eval. */
+fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, const double *g_dev,
+                            const double *md_dev, const int64_t *ed_dev, double *grad_a_dev,
+                            double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
+                            hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Same-GPU baseline: Horner's rule on the full polynomial (Section 1).      */
 /* ------------------------------------------------------------------------- */

@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
     L.ora_eval_deriv.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int64, _f64p, _i64p, _f64p, _i64p,
                                  _f64p, _i64p, _f64p, _i64p, ctypes.c_int]
     L.ora_horner.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
+    L.ora_adjoint_coef.argtypes = [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64, ctypes.c_int64,
+                                   _f64p, _i64p, _f64p, _i64p]
     L.ora_absum.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
     _LIB = L
     return L
@@ -185,6 +187,32 @@ class OraclePlan:
         return {"m": m.view(np.complex128), "e": e, "dwin_m": dm, "dwin_e": de,
                 "md": md.view(np.complex128), "ed": ed, "ddwin_m": ddm, "ddwin_e": dde}
 
+
+    def adjoint(self, z, g) -> dict:
+        """Reverse mode of Q_lambda at the points z for upstream gradients g, in the
+        convention of complex reverse mode (upstream gradient times the conjugate
+        derivative), the kept set held fixed:
+          grad_a[k] = sum over the points keeping k of g_j conj(z_j)^k   (as ga_m 2^ga_e,
+                      with its scale sum |g_j| |z_j|^k as ga_scale_m 2^ga_scale_e),
+          grad_z[j] = g_j conj(Q'_lambda(z_j))                            (as gz_m 2^gz_e,
+                      with its scale |g_j| sum |k a_k||z_j|^(k-1) as gz_scale_m 2^gz_scale_e).
+        """
+        zri = _as_ri(np.atleast_1d(z))
+        gri = _as_ri(np.atleast_1d(g))
+        n = zri.shape[0] // 2
+        if gri.shape[0] != 2 * n:
+            raise ValueError("z and g differ in length")
+        ga = np.zeros(2 * (self.d + 1), np.float64)
+        gae = np.zeros(self.d + 1, np.int64)
+        sm = np.zeros(self.d + 1, np.float64)
+        se = np.zeros(self.d + 1, np.int64)
+        lib().ora_adjoint_coef(self._h, _ptr(zri, _f64p), _ptr(gri, _f64p), n, self.d, _ptr(ga, _f64p),
+                               _ptr(gae, _i64p), _ptr(sm, _f64p), _ptr(se, _i64p))
+        dv = self.eval_deriv(zri.view(np.complex128))
+        gc = gri.view(np.complex128)
+        return {"ga_m": ga.view(np.complex128), "ga_e": gae, "ga_scale_m": sm, "ga_scale_e": se,
+                "gz_m": gc * np.conj(dv["md"]), "gz_e": dv["ed"],
+                "gz_scale_m": np.abs(gc) * dv["ddwin_m"], "gz_scale_e": dv["ddwin_e"]}
 
 def precondition(coeffs, p: int = 53, offset: int | None = None) -> OraclePlan:
     return OraclePlan(coeffs, p, offset)

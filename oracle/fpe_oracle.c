@@ -19,6 +19,10 @@
  *   ora_horner        P(z) = sum_k a_k z^k by compensated Horner        Section 4.1 (the plain definition);
  *                     (error-free transforms), unbounded exponent       compensated Horner is cited in Section 1
  *   ora_absum         D(z) = sum_k |a_k| |z|^k                          tolerance scale of the parity metric
+ *   ora_eval_deriv    Q'_lambda(z) = sum over the same kept terms of    derivative of eq. (reducedQlambda);
+ *                     k a_k z^(k-1)                                      Newton's method, Section 7.2
+ *   ora_adjoint_coef  grad_a[k] = sum over the points keeping k of      reverse mode of eq. (reducedQlambda)
+ *                     g_j conj(z_j)^k                                    (linear in a; kept set held fixed)
  *
  * Precision: every decision that yields an integer (scales, hull, G_p, the
  * argmax, the window ends) is taken in exact integer arithmetic or in FP64,
@@ -699,4 +703,46 @@ void ora_absum(const double *coef, int64_t d, const double *z, int64_t n,
 {
     ora_job J = { 2, NULL, coef, d, z, 0, 0, dm, de, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
     ora_run(J, n, nthreads);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Reverse mode of the evaluation with respect to the coefficients.          */
+/* Q_lambda(z) (eq. reducedQlambda) is linear in a: its partial derivative    */
+/* in a_k is z^k for the kept k (G_p within [l, r], held fixed) and 0         */
+/* otherwise.  With upstream gradients g_j and the convention of complex      */
+/* reverse mode (gradient = upstream gradient times the conjugate             */
+/* derivative), grad_a[k] = sum over the points j keeping k of                */
+/* g_j conj(z_j)^k, and its scale sum of |g_j| |z_j|^k over the same terms.    */
+/* One thread: the points are summed in input order into double-double        */
+/* accumulators with a separate exponent.                                     */
+/* ------------------------------------------------------------------------- */
+void ora_adjoint_coef(const ora_plan *P, const double *z, const double *g, int64_t n, int64_t d,
+                      double *ga_m, int64_t *ga_e, double *sc_m, int64_t *sc_e)
+{
+    xc_t *acc = malloc(sizeof(xc_t) * (size_t)(d + 1));
+    xr_t *sc = malloc(sizeof(xr_t) * (size_t)(d + 1));
+    for (int64_t k = 0; k <= d; ++k) { acc[k] = xc_from(0.0, 0.0); sc[k] = (xr_t){ 0.0, 0 }; }
+    for (int64_t j = 0; j < n; ++j) {
+        double zr = z[2 * j], zi = z[2 * j + 1];
+        ora_res o;
+        ora_eval1(P, zr, zi, 0, &o);               /* the window [l, r] of this point */
+        if (!isfinite(zr) || !isfinite(zi) || o.l > o.r) continue;
+        xc_t gj = xc_from(g[2 * j], g[2 * j + 1]);
+        double gabs = hypot(g[2 * j], g[2 * j + 1]);
+        xc_t zc = xc_from(zr, -zi);                /* conj(z) */
+        xc_t pw = xc_pow(zc, o.l);                 /* conj(z)^l, then one product per k */
+        for (int64_t k = o.l; k <= o.r; ++k) {
+            if (P->good[k]) {
+                acc[k] = xc_add(acc[k], xc_mul(gj, pw));
+                sc[k] = xr_add(sc[k], xr_norm((xr_t){ gabs * hypot(pw.re.hi, pw.im.hi), pw.e }));
+            }
+            if (k < o.r) pw = xc_mul(pw, zc);
+        }
+    }
+    for (int64_t k = 0; k <= d; ++k) {
+        xc_out(acc[k], ga_m + 2 * k, ga_e + k);
+        sc_m[k] = sc[k].m; sc_e[k] = sc[k].e;
+    }
+    free(acc);
+    free(sc);
 }

@@ -10,6 +10,9 @@ There is no fallback: if libfpe.so is missing, loading fails with an error.
     m, e, terms, window = plan.eval(z, terms=True, window=True)
     m, e = horner_eval(coeffs, z)          # same-GPU Horner baseline
     to_complex(m, e)                       # m * 2**e as complex128 (may overflow)
+    m, e, md, ed = plan.eval_deriv(z)      # and Q' = md * 2**ed through the same window
+    ga, gz = plan.adjoint(z, g)            # reverse mode for upstream gradients g
+    q = fpe_eval(coeffs, z)                # differentiable (torch.autograd)
 """
 from __future__ import annotations
 
@@ -75,6 +78,8 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_deriv.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_newton_step.restype = i32
     L.fpe_newton_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_eval_adjoint.restype = i32
+    L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_horner_eval.restype = i32
     L.fpe_horner_eval.argtypes = [vp, i64, vp, i64, vp, vp, vp]
     L.fpe_profile_enable.restype = i32
@@ -239,6 +244,74 @@ class Plan:
         _check(lib().fpe_newton_step(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
                                      ed.data_ptr(), zn.data_ptr(), ws, nb, _stream(stream)))
         return zn, m, e, md, ed
+
+    def adjoint(self, z, g, md=None, ed=None, grad_a: bool = True, grad_z: bool = True, stream=None):
+        """Reverse mode of Q_lambda for upstream gradients g (complex convention:
+        upstream gradient times the conjugate derivative; the kept terms held
+        fixed).  Returns (grad_a [d + 1] or None, grad_z [n] or None):
+        grad_a[k] = sum of g_j conj(z_j)^k over the points keeping k,
+        grad_z[j] = g_j conj(Q'(z_j)), Q' = md 2^ed from eval_deriv (computed
+        here when not given)."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        g = _dev_complex(g, "g")
+        n = z.shape[0]
+        if g.shape != z.shape:
+            raise ValueError("g must have the shape of z")
+        if grad_z and (md is None or ed is None):
+            _, _, md, ed = self.eval_deriv(z, stream=stream)
+        ga = torch.empty(self.d + 1, dtype=torch.complex128, device=z.device) if grad_a else None
+        gz = torch.empty(n, dtype=torch.complex128, device=z.device) if grad_z else None
+        if grad_z:
+            md = _dev_complex(md, "md")
+            ed = ed.contiguous()
+        ws, nb = self.workspace(n)
+        _check(lib().fpe_eval_adjoint(self._h, z.data_ptr(), n, g.data_ptr(),
+                                      md.data_ptr() if grad_z else None, ed.data_ptr() if grad_z else None,
+                                      ga.data_ptr() if ga is not None else None,
+                                      gz.data_ptr() if gz is not None else None, ws, nb, _stream(stream)))
+        return ga, gz
+
+
+def _fpe_function():
+    torch = _torch()
+
+    class FPEEval(torch.autograd.Function):
+        """Q_lambda(z) as complex128 for coefficients a (precondition + eval), with
+        the backward pass of fpe_eval_adjoint.  The map is piecewise polynomial:
+        the kept set (G_p and the windows) is held fixed under differentiation."""
+
+        @staticmethod
+        def forward(ctx, coeffs, z, p):
+            plan = Plan(coeffs.detach(), p)
+            zd = z.detach()
+            if ctx.needs_input_grad[1]:
+                m, e, md, ed = plan.eval_deriv(zd)
+            else:
+                m, e = plan.eval(zd)
+                md = ed = None
+            ctx.plan = plan
+            ctx.z, ctx.md, ctx.ed = zd, md, ed
+            return to_complex(m, e)
+
+        @staticmethod
+        def backward(ctx, g):
+            ga, gz = ctx.plan.adjoint(ctx.z, g.contiguous(), ctx.md, ctx.ed,
+                                      grad_a=ctx.needs_input_grad[0], grad_z=ctx.needs_input_grad[1])
+            return ga, gz, None
+
+    return FPEEval
+
+
+_FPE_FN = None
+
+
+def fpe_eval(coeffs, z, p: int = 53):
+    """Differentiable Q_lambda(z) (complex128, may overflow to inf like to_complex)."""
+    global _FPE_FN
+    if _FPE_FN is None:
+        _FPE_FN = _fpe_function()
+    return _FPE_FN.apply(_dev_complex(coeffs, "coeffs"), _dev_complex(z, "z"), p)
 
 
 def precondition(coeffs, p: int = 53, stream=None) -> Plan:

@@ -158,7 +158,7 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, 
         er = (long long)floor(N) + 2;
         key = lambda_bin(lam);
     }
-    if (done) {
+    if (done && m_out) {
         m_out[j] = mo;
         e_out[j] = eo;
         // the kept terms of a finished point are at most a_0: derivative 0
@@ -661,6 +661,68 @@ __device__ __forceinline__ void run_steps(Acc<D> &a, double zr, double zi, const
 constexpr int kWindowThreads = 256;
 constexpr int kWindowWaves = kWindowThreads / kWave;
 
+// State of the chained powers of one segment (see tile_power).
+struct PowState {
+    int chain_c = -1;          // chunk of the chained power; -1: none
+    bool have_zc = false;      // w^C is in LDS
+    bool xv = false;           // this lane's chained power is w^(chain_c C)
+};
+
+// z^lo for the lanes of tile (g, c), as (pr + i pi) 2^pe times 2^(lo ez):
+// w^l by binary powering for lanes whose window starts in this chunk (lo = l),
+// the chained w^(c C) for lanes that started earlier (lo = c C), advanced by one
+// product per chunk from the anchor w^(m C), m = c - c mod kAnchor, by
+// cpow_chunk_start's recipe, so that every wavefront gets the same bits for the
+// same chunk.  s_ch / s_che hold per thread the chained power and w^C.
+__device__ __forceinline__ void tile_power(PowState &ps, int l, int lo, bool act, int c, int C, double wr, double wi,
+                                           double (*s_ch)[kWindowThreads], long long (*s_che)[kWindowThreads], int t,
+                                           double &pr, double &pi, long long &pe) {
+    const int c0 = c * C;
+    const bool cont = act && l < c0;
+    pr = 1.0; pi = 0.0; pe = 0;
+    const bool any_cont = __ballot(cont) != 0;
+    // a continuing lane advances its chained power by one product if it holds
+    // w^((c - 1) C) and c is not an anchor; otherwise it starts from the anchor
+    const bool step_ok = ps.chain_c >= 0 && ps.chain_c == c - 1 && c % kAnchor != 0;
+    const bool use_chain = cont && ps.xv && step_ok;
+    const bool need_anchor = cont && !use_chain;
+    // at most two rounds of one binary powering each (one call site keeps the
+    // register footprint down): round 0, once per segment, w^C; round 1, the
+    // anchors of continuing lanes that need them and w^lo of lanes whose window
+    // starts in this chunk
+    const bool need1 = __ballot(need_anchor || (!cont && act && lo > 0)) != 0;
+    const int rd_end = need1 ? 1 : 0;
+#pragma nounroll
+    for (int rd = (any_cont && !ps.have_zc) ? 0 : 1; rd <= rd_end; ++rd) {
+        const int n = rd == 0 ? C : (need_anchor ? (c - c % kAnchor) * C : (!cont && act ? lo : 0));
+        double qr_, qi_;
+        long long qe = 0;
+        cpow_dd(wr, wi, n, qr_, qi_, qe);
+        if (rd == 0) {
+            s_ch[2][t] = qr_; s_ch[3][t] = qi_; s_che[1][t] = qe;
+        } else {
+            pr = qr_; pi = qi_; pe = qe;
+        }
+    }
+    if (any_cont) {
+        ps.have_zc = true;
+        if (cont) {
+            const double zcr = s_ch[2][t], zci = s_ch[3][t];
+            const long long zce = s_che[1][t];
+            double xr, xi;
+            long long xe;
+            int j0;
+            if (use_chain) { xr = s_ch[0][t]; xi = s_ch[1][t]; xe = s_che[0][t]; j0 = c - 1; }
+            else { xr = pr; xi = pi; xe = pe; j0 = c - c % kAnchor; }
+            for (int j = j0; j < c; ++j) cmul_renorm(xr, xi, xe, zcr, zci, zce);
+            s_ch[0][t] = xr; s_ch[1][t] = xi; s_che[0][t] = xe;
+            pr = xr; pi = xi; pe = xe;
+        }
+        ps.xv = cont;
+        ps.chain_c = c;
+    }
+}
+
 // fixed-point words per lane and window-wavefront slot: the sums of Q, then of Q'
 constexpr int kSlotWords = 8;
 
@@ -697,7 +759,8 @@ __device__ __forceinline__ void fix_out(const DevPlan &P, long long a0, long lon
 // With D, the same pass also sums the derivative of the kept terms,
 // Q'(z) = sum k a_k z^(k-1) over G_p within [l, r], into (md_out, ed_out).
 template <bool D>
-__global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *__restrict__ m_out,
+__global__ __launch_bounds__(kWindowThreads) __attribute__((amdgpu_waves_per_eu(D ? 5 : 6)))
+void k_window(DevPlan P, double2 *__restrict__ m_out,
                                                            long long *__restrict__ e_out,
                                                            double2 *__restrict__ md_out,
                                                            long long *__restrict__ ed_out, EvalWs W) {
@@ -752,11 +815,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
         // without a point); z itself is rebuilt exactly from w when needed
         const int ez = valid ? exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y))) : 0;
         const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
-        // w^(c C) for the lanes that entered the window in an earlier chunk,
-        // advanced by one product per chunk (cpow_chunk_start's recipe)
-        int chain_c = -1;                                 // chunk of the chained power; -1: none
-        bool have_zc = false;
-        bool xv = false;                                  // this lane's chained power is w^(chain_c C)
+        PowState pw;                                      // chained powers of this segment
         for (int k = 0; k < kAccWords; ++k) s_acc[k][threadIdx.x] = 0;
         for (;;) {
             // ---- tile (g, c): this lane's part [lo, hi] of chunk c
@@ -770,52 +829,10 @@ __global__ __launch_bounds__(kWindowThreads) void k_window(DevPlan P, double2 *_
             if (Khi >= Klo) {
                 // z^lo first: w^l by binary powering where the window starts in this
                 // chunk, the chained w^(c C) where it started earlier
-                const bool cont = act && l < c0;
-                double pr = 1.0, pi = 0.0;
-                long long pe = 0;
                 const int t = threadIdx.x;
-                const bool any_cont = __ballot(cont) != 0;
-                // a continuing lane advances its chained power by one product if it
-                // holds w^((c - 1) C) and c is not an anchor; otherwise it starts
-                // from the anchor w^(m C), m = c - c mod kAnchor
-                const bool step_ok = chain_c >= 0 && chain_c == c - 1 && c % kAnchor != 0;
-                const bool use_chain = cont && xv && step_ok;
-                const bool need_anchor = cont && !use_chain;
-                // at most two rounds of one binary powering each (one call site keeps
-                // the register footprint down): round 0, once per segment, w^C;
-                // round 1, the anchors of continuing lanes that need them and w^lo of
-                // lanes whose window starts in this chunk
-                const bool need1 = __ballot(need_anchor || (!cont && act && lo > 0)) != 0;
-                const int rd_end = need1 ? 1 : 0;
-#pragma nounroll
-                for (int rd = (any_cont && !have_zc) ? 0 : 1; rd <= rd_end; ++rd) {
-                    const int n = rd == 0 ? C : (need_anchor ? (c - c % kAnchor) * C : (!cont && act ? lo : 0));
-                    double qr_, qi_;
-                    long long qe = 0;
-                    cpow_dd(wr, wi, n, qr_, qi_, qe);
-                    if (rd == 0) {
-                        s_ch[2][t] = qr_; s_ch[3][t] = qi_; s_che[1][t] = qe;
-                    } else {
-                        pr = qr_; pi = qi_; pe = qe;
-                    }
-                }
-                if (any_cont) {
-                    have_zc = true;
-                    if (cont) {
-                        const double zcr = s_ch[2][t], zci = s_ch[3][t];
-                        const long long zce = s_che[1][t];
-                        double xr, xi;
-                        long long xe;
-                        int j0;
-                        if (use_chain) { xr = s_ch[0][t]; xi = s_ch[1][t]; xe = s_che[0][t]; j0 = c - 1; }
-                        else { xr = pr; xi = pi; xe = pe; j0 = c - c % kAnchor; }
-                        for (int j = j0; j < c; ++j) cmul_renorm(xr, xi, xe, zcr, zci, zce);
-                        s_ch[0][t] = xr; s_ch[1][t] = xi; s_che[0][t] = xe;
-                        pr = xr; pi = xi; pe = xe;
-                    }
-                    xv = cont;
-                    chain_c = c;
-                }
+                double pr, pi;
+                long long pe;
+                tile_power(pw, l, lo, act, c, C, wr, wi, s_ch, s_che, t, pr, pi, pe);
                 Acc<D> acc;
                 const double zr = ldexp(wr, ez), zi = ldexp(wi, ez);
                 if (Ahi >= Alo) {
@@ -961,14 +978,157 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
     }
 }
 
-int g_num_cu = 0;
-int g_window_blocks_per_cu[2] = {0, 0};   // without and with the derivative
+// sum over the 64 lanes (every lane gets it)
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
 
-// wavefronts of the window kernel: as many as are resident at once on the
-// device (the partition hands each one an equal share, so none may wait for a
-// second round)
-int64_t window_waves(bool deriv) {
-    const int b = g_window_blocks_per_cu[deriv ? 1 : 0];
+// Adjoint of the window sums with respect to the coefficients: for upstream
+// gradients gin_j (per point, input order), grad_a[k] += sum over the points j
+// whose kept terms include k (k in G_p within [l_j, r_j]) of gin_j conj(z_j)^k
+// (the convention of complex autograd: the gradient of a holomorphic map is
+// the upstream gradient times the conjugate derivative, here d Q / d a_k = z^k).
+// Same tiles and partition as k_window: each lane starts from gin conj(z^lo)
+// (z^lo by tile_power) and multiplies by conj(z) per step, mantissa and
+// exponent apart, so that a term is rounded to the double range only when it
+// is emitted; the 64 lanes' terms of each k are summed across the wavefront
+// and added to grad_a[k] (FP64 atomics: the order of the additions, hence the
+// last bits, can vary).
+__global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const double2 *__restrict__ gin,
+                                                            double2 *__restrict__ grad_a, EvalWs W) {
+    const int lane = threadIdx.x % kWave;
+    const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
+    __shared__ double s_ch[4][kWindowThreads];
+    __shared__ long long s_che[2][kWindowThreads];
+    if (w >= W.n_waves) return;
+    const int nvalid = valid_points(W);
+    const int G = (int)W.n_groups;
+    const int C = P.chunk;
+    int g, c, ge, ce;
+    {
+        const int2 st = W.wstart[w], en = W.wstart[w + 1];
+        g = __builtin_amdgcn_readfirstlane(st.x);
+        c = __builtin_amdgcn_readfirstlane(st.y);
+        ge = __builtin_amdgcn_readfirstlane(en.x);
+        ce = __builtin_amdgcn_readfirstlane(en.y);
+    }
+    resolve_tile(W, C, g, c);
+    resolve_tile(W, C, ge, ce);
+    while (g < G && !(g == ge && c == ce)) {
+        const int ghi = __builtin_amdgcn_readfirstlane(W.ghi[g]);
+        const int chi = ghi / C;
+        const int idx = g * kWave + lane;
+        const bool valid = idx < nvalid;
+        PointRec rc;
+        if (valid) rc = W.srec[idx];
+        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.eref = 0; }
+        const int l = rc.l, r = rc.r;
+        const int ez = valid ? exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y))) : 0;
+        const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
+        // g = (gr + i gi) 2^eg with max(|gr|, |gi|) in [1/2, 1) (0 for no point)
+        double gr = 0.0, gi = 0.0;
+        int eg = 0;
+        if (valid) {
+            const double2 gj = gin[W.sperm[idx]];
+            const double gm = fmax(fabs(gj.x), fabs(gj.y));
+            if (gm != 0.0 && isfinite(gm)) { eg = exp_of(gm); gr = ldexp(gj.x, -eg); gi = ldexp(gj.y, -eg); }
+            else { gr = gj.x; gi = gj.y; }
+        }
+        PowState pw;
+        for (;;) {
+            const int c0 = c * C, c1 = c0 + C - 1;
+            const int lo = max(l, c0), hi = min(r, c1);
+            const bool act = valid && lo <= hi;
+            const int Khi = __builtin_amdgcn_readfirstlane(wave_max(act ? hi : INT_MIN));
+            const int Klo = __builtin_amdgcn_readfirstlane(wave_min(act ? lo : INT_MAX));
+            if (Khi >= Klo) {
+                const int t = threadIdx.x;
+                double pr, pi;
+                long long pe;
+                tile_power(pw, l, lo, act, c, C, wr, wi, s_ch, s_che, t, pr, pi, pe);
+                // term k = (tr + i ti) 2^E: the mantissa g conj(w^k) (|w| in [1/2, 2^(1/2)),
+                // so over one chunk it stays within [2^-514, 2^258]) and the exponent
+                // eg + pe + k ez apart; only the emitted term is scaled (and may
+                // saturate or flush)
+                double tr = fma(gr, pr, gi * pi);
+                double ti = fma(gi, pr, -gr * pi);
+                long long E = (long long)eg + pe + (long long)lo * ez;
+                for (int k = Klo; k <= Khi; ++k) {
+                    const bool on = act && k >= lo && k <= hi;
+                    double vr = 0.0, vi = 0.0;
+                    if (on) {
+                        const int sh = (int)(E < -2200 ? -2200 : (E > 2200 ? 2200 : E));
+                        vr = ldexp(tr, sh);
+                        vi = ldexp(ti, sh);
+                        const double nr = fma(tr, wr, ti * wi);       // times conj(w)
+                        ti = fma(ti, wr, -tr * wi);
+                        tr = nr;
+                        E += ez;
+                    }
+                    // only terms of G_p: their coefficients are the nonzero entries
+                    // of the masked table
+                    const double2 a = P.coef[k];
+                    if (a.x != 0.0 || a.y != 0.0) {
+                        vr = wave_sum(vr);
+                        vi = wave_sum(vi);
+                        if (lane == 0 && (vr != 0.0 || vi != 0.0)) {
+                            atomicAdd(&grad_a[k].x, vr);
+                            atomicAdd(&grad_a[k].y, vi);
+                        }
+                    }
+                }
+            }
+            if (c == chi || (g == ge && c + 1 == ce)) break;
+            ++c;
+        }
+        if (c < chi) { ++c; }
+        else { ++g; c = -1; resolve_tile(W, C, g, c); }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero2(double2 *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = make_double2(0.0, 0.0);
+}
+
+// Per point: the gradient with respect to z, gin conj(Q'(z)) with Q' = md 2^ed
+// (NaN for a non-finite z), and the contribution of z = 0 to a_0: there the
+// kept terms are a_0 alone (when a_0 != 0), so grad_a[0] += gin.
+__global__ __launch_bounds__(256) void k_grad_z(DevPlan P, const double2 *__restrict__ z, int n,
+                                                const double2 *__restrict__ gin, const double2 *__restrict__ md,
+                                                const long long *__restrict__ ed, double2 *__restrict__ grad_z,
+                                                double2 *__restrict__ grad_a) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double2 zz = z[j], g = gin[j];
+    if (grad_z) {
+        if (!isfinite(zz.x) || !isfinite(zz.y)) {
+            grad_z[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
+        } else {
+            const double2 b = md[j];
+            long long sh = ed[j];
+            sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
+            grad_z[j] = make_double2(ldexp(fma(g.x, b.x, g.y * b.y), (int)sh), ldexp(fma(g.y, b.x, -g.x * b.y), (int)sh));
+        }
+    }
+    if (grad_a && zz.x == 0.0 && zz.y == 0.0 && P.nh > 0 && P.v == 0) {
+        atomicAdd(&grad_a[0].x, g.x);
+        atomicAdd(&grad_a[0].y, g.y);
+    }
+}
+
+int g_num_cu = 0;
+// the kernels that run the (group, chunk) tiles: values, values and
+// derivatives, adjoint
+enum TileKernel { kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2 };
+int g_window_blocks_per_cu[3] = {0, 0, 0};
+
+// wavefronts of a tile kernel: as many as are resident at once on the device
+// (the partition hands each one an equal share, so none may wait for a second
+// round)
+int64_t window_waves(int kind) {
+    const int b = g_window_blocks_per_cu[kind];
     return (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (b > 0 ? b : 1) * kWindowWaves;
 }
 
@@ -988,18 +1148,15 @@ hipError_t prof_event(hipEvent_t *ev) {
 // compute units and resident window workgroups per compute unit (once per process)
 hipError_t device_setup() {
     if (g_num_cu > 0) return hipSuccess;
-    int dev = 0, ncu = 0, nb0 = 0, nb1 = 0;
+    int dev = 0, ncu = 0, nb[3] = {0, 0, 0};
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, reinterpret_cast<const void *>(k_window<false>),
-                                                        kWindowThreads, 0);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, reinterpret_cast<const void *>(k_window<true>),
-                                                        kWindowThreads, 0);
+    const void *kern[3] = {reinterpret_cast<const void *>(k_window<false>),
+                           reinterpret_cast<const void *>(k_window<true>), reinterpret_cast<const void *>(k_adjoint)};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb[i], kern[i], kWindowThreads, 0);
     if (e != hipSuccess) return e;
-    g_window_blocks_per_cu[0] = nb0 > 0 ? nb0 : 1;
-    g_window_blocks_per_cu[1] = nb1 > 0 ? nb1 : 1;
+    for (int i = 0; i < 3; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
     g_num_cu = ncu > 0 ? ncu : 256;
     return hipSuccess;
 }
@@ -1042,7 +1199,7 @@ int cost_shift_for(const DevPlan &P, int64_t n) {
     return -1;
 }
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, bool deriv) {
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
@@ -1072,9 +1229,10 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
     w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
-    // one workspace serves both window variants
-    const int64_t nw_max = std::max(window_waves(false), window_waves(true));
-    w.n_waves = window_waves(deriv);
+    // one workspace serves every tile kernel
+    const int64_t nw_max = std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
+                                    window_waves(kTileAdjoint));
+    w.n_waves = window_waves(kind);
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
@@ -1096,9 +1254,31 @@ extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t
     if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
     if (cost_shift_for(plan->dev, n) < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
     FPE_HIP_CHECK(device_setup());
-    *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, false);
+    *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, kTileValue);
     set_error("");
     return FPE_OK;
+}
+
+// The kernels before the tile kernel: bounds, sort, groups, partition.
+static hipError_t launch_front(const DevPlan &P, const double2 *z, int ni, double2 *m, long long *e, double2 *md,
+                               long long *ed, int32_t *terms, long long *win, const EvalWs &W, hipStream_t stream) {
+    const unsigned sb = (unsigned)W.n_sort_blocks;
+    const unsigned pb = (unsigned)((ni + 1023) / 1024);
+    const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
+    k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, md, ed, terms, win, W);
+    if (P.nh > 0) {
+        const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
+        k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
+        k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
+        k_groups<<<(unsigned)nblk_g, 1024, 0, stream>>>(P, W);
+        if (nblk_g > kPartLds) {
+            const int nseg = (nblk_g + kSeg - 1) / kSeg;
+            k_scan_seg<<<(unsigned)nseg, 1024, 0, stream>>>(W.gblk_sum, W.gblk_pre, nblk_g, W.gseg_sum);
+            k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg, W.gseg_off, W.ctl + 0);
+        }
+        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 1023) / 1024), 1024, 0, stream>>>(P, W);
+    }
+    return hipGetLastError();
 }
 
 static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
@@ -1118,7 +1298,7 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
         reinterpret_cast<uintptr_t>(m_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv);
+    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue);
     const DevPlan &P = plan->dev;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
     double2 *m = reinterpret_cast<double2 *>(m_dev);
@@ -1127,23 +1307,10 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
     long long *ed = reinterpret_cast<long long *>(ed_dev);
     long long *win = reinterpret_cast<long long *>(window_dev);
     const int ni = (int)n;
-    const unsigned sb = (unsigned)W.n_sort_blocks;
-    const unsigned pb = (unsigned)((n + 1023) / 1024);
-    const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
 
     FPE_HIP_CHECK(device_setup());
-    k_bounds<<<sb, kBoundsThreads, 0, stream>>>(P, z, ni, m, e, md, ed, terms_dev, win, W);
+    FPE_HIP_CHECK(launch_front(P, z, ni, m, e, md, ed, terms_dev, win, W, stream));
     if (P.nh > 0) {
-        const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
-        k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
-        k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
-        k_groups<<<(unsigned)nblk_g, 1024, 0, stream>>>(P, W);
-        if (nblk_g > kPartLds) {
-            const int nseg = (nblk_g + kSeg - 1) / kSeg;
-            k_scan_seg<<<(unsigned)nseg, 1024, 0, stream>>>(W.gblk_sum, W.gblk_pre, nblk_g, W.gseg_sum);
-            k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg, W.gseg_off, W.ctl + 0);
-        }
-        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 1023) / 1024), 1024, 0, stream>>>(P, W);
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
         if (g_prof.on) {
@@ -1178,7 +1345,7 @@ extern "C" fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n, 
 extern "C" fpe_status fpe_eval_deriv(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev,
                                      int64_t *e_dev, double *md_dev, int64_t *ed_dev, void *workspace_dev,
                                      size_t workspace_bytes, hipStream_t stream) {
-    if (!md_dev || !ed_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (n > 0 && (!md_dev || !ed_dev)) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     return eval_impl(plan, z_dev, n, m_dev, e_dev, md_dev, ed_dev, nullptr, nullptr, workspace_dev,
                      workspace_bytes, stream);
 }
@@ -1220,6 +1387,49 @@ extern "C" fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int6
         reinterpret_cast<const double2 *>(z_dev), (int)n, reinterpret_cast<const double2 *>(m_dev),
         reinterpret_cast<const long long *>(e_dev), reinterpret_cast<const double2 *>(md_dev),
         reinterpret_cast<const long long *>(ed_dev), reinterpret_cast<double2 *>(z_out_dev));
+    FPE_HIP_CHECK(hipGetLastError());
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, const double *g_dev,
+                                       const double *md_dev, const int64_t *ed_dev, double *grad_a_dev,
+                                       double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
+                                       hipStream_t stream) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    size_t need = 0;
+    fpe_status st = fpe_eval_workspace_size(plan, n, &need);
+    if (st != FPE_OK) return st;
+    if (n > 0 && (!z_dev || !g_dev || !workspace_dev || (grad_z_dev && (!md_dev || !ed_dev))))
+        return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (n > 0 && workspace_bytes < need)
+        return fail(FPE_ERR_WORKSPACE, "eval workspace too small: need " + std::to_string(need));
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0 || reinterpret_cast<uintptr_t>(z_dev) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(g_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(grad_a_dev) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(grad_z_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
+        return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
+    const DevPlan &P = plan->dev;
+    const int64_t na = plan->d + 1;
+    double2 *ga = reinterpret_cast<double2 *>(grad_a_dev);
+    FPE_HIP_CHECK(device_setup());
+    if (ga) k_zero2<<<(unsigned)((na + 255) / 256), 256, 0, stream>>>(ga, na);
+    if (n > 0) {
+        EvalWs W;
+        eval_workspace_bytes(P, n, &W, workspace_dev, kTileAdjoint);
+        const double2 *z = reinterpret_cast<const double2 *>(z_dev);
+        const double2 *g = reinterpret_cast<const double2 *>(g_dev);
+        const int ni = (int)n;
+        if (ga) {
+            FPE_HIP_CHECK(launch_front(P, z, ni, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, stream));
+            if (P.nh > 0)
+                k_adjoint<<<(unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves), kWindowThreads, 0, stream>>>(
+                    P, g, ga, W);
+        }
+        if (ga || grad_z_dev)
+            k_grad_z<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
+                P, z, ni, g, reinterpret_cast<const double2 *>(md_dev), reinterpret_cast<const long long *>(ed_dev),
+                reinterpret_cast<double2 *>(grad_z_dev), ga);
+    }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");
     return FPE_OK;

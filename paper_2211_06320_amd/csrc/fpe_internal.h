@@ -67,7 +67,7 @@ struct EvalWs {
     int32_t tab_ib;               // bins per table-scan segment
 };
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, bool deriv);
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind);
 
 // Read-only tables are read through the constant address space in device code:
 // a wave-uniform index then becomes a scalar load, one per wavefront, broadcast

@@ -1,0 +1,276 @@
+"""Reverse mode (fpe_eval_adjoint) on the HIP path against the oracle, and the
+autograd wrapper against central finite differences.
+
+Tolerance of grad_a[k], relative to its scale S[k] = sum |g_j| |z_j|^k over the
+same terms, derived from the kernel's arithmetic (u = 2^-53): the start power
+z^lo is within 24 u normwise (chained chunk powers), the product with g adds
+2 u, each of the at most C - 1 = 511 further products by conj(z) adds 2 u
+(complex product with FMA), the 64-lane tree sum 6 u and each of the W
+wavefront partials added by atomics 1 u:  u (2 C + 40 + W).  grad_z is g times
+conj(Q'), Q' within 2^-44 of its scale: 2^-43 |g| sum |k a_k||z|^(k-1).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_06320_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+CHUNK = 512
+
+
+def tol_grad_a(w_partials: int) -> float:
+    return U * (2 * CHUNK + 40 + w_partials)
+
+
+@pytest.fixture(scope="module")
+def fpe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2211_06320_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.device("cuda:0"))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def scaled_g(c, z, seed, limit=1000):
+    """Upstream gradients whose terms g_j conj(z_j)^k stay within the double
+    range: g_j = (random) 2^-s_j with s_j the largest lambda_j k of the point's
+    window; 0 where that needs |s_j| > limit."""
+    rng = np.random.default_rng(seed)
+    r = oracle.precondition(c, 53).eval(z)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lam = np.log2(np.abs(z))
+        s = np.where(r["l"] <= r["r"], np.maximum(lam * r["l"], lam * r["r"]), 0.0)
+    s = np.where(np.isfinite(s), np.ceil(s), 0.0)
+    g = (rng.normal(size=len(z)) + 1j * rng.normal(size=len(z))) * np.exp2(-np.clip(s, -limit, limit))
+    g[np.abs(s) > limit] = 0
+    return g
+
+
+def xval(m, e):
+    e = np.clip(np.asarray(e, np.int64), -3000, 3000)
+    with np.errstate(over="ignore"):
+        return np.ldexp(np.asarray(m).real, e) + 1j * np.ldexp(np.asarray(m).imag, e)
+
+
+def check(fpe, c, z, g, label, w_partials=None):
+    plan = fpe.precondition(to_dev(c), 53)
+    ga, gz = plan.adjoint(to_dev(z), to_dev(g))
+    torch.cuda.synchronize()
+    ga, gz = ga.cpu().numpy(), gz.cpu().numpy()
+    ref = oracle.precondition(c, 53).adjoint(z, g)
+    S = np.ldexp(ref["ga_scale_m"], np.clip(ref["ga_scale_e"], -3000, 3000))
+    want = xval(ref["ga_m"], ref["ga_e"])
+    zero = S == 0
+    assert (ga[zero] == 0).all()
+    ok = (S >= 2.0 ** -1000) & (S <= 2.0 ** 1000)
+    err = np.abs(ga[ok] - want[ok]) / S[ok]
+    if w_partials is None:
+        w_partials = math.ceil(len(z) / 64)
+    tol = tol_grad_a(w_partials)
+    worst = float(err.max(initial=0.0))
+    say(f"  {label}: grad_a max scaled error {worst:.3e} (tol {tol:.3e}) on {ok.sum()} coefficients")
+    assert worst <= tol, (worst, math.log2(max(worst, 1e-300)))
+    # grad_z
+    fin = np.isfinite(z.real) & np.isfinite(z.imag)
+    assert np.isnan(gz[~fin].real).all()
+    gs = ref["gz_scale_m"][fin]
+    zs = gs == 0
+    assert (gz[fin][zs] == 0).all()
+    errz = oracle.scaled_error(gz[fin][~zs], np.zeros((~zs).sum(), np.int64), ref["gz_m"][fin][~zs],
+                               ref["gz_e"][fin][~zs], gs[~zs], ref["gz_scale_e"][fin][~zs])
+    wz = float(errz.max(initial=0.0))
+    say(f"  {label}: grad_z max scaled error {wz:.3e} on {(~zs).sum()} points")
+    assert wz <= 2.0 ** -43
+    return ga, gz
+
+
+def test_adjoint_small(fpe):
+    wl = workloads.workload("uniform_d1000", n_points=1500)
+    rng = np.random.default_rng(61)
+    lam = rng.uniform(-0.5, 0.9, 1500)
+    near = 2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, 1500))
+    z = np.concatenate([wl.points, near, [0, np.nan, 1e300 + 1e300j, 1.0, -1j]])
+    g = scaled_g(wl.coeffs, z, 62)
+    g[-5:] = [1 + 2j, 1, 0, 0.5, 0.25j]
+    check(fpe, wl.coeffs, z, g, "uniform d=1000")
+
+
+def test_adjoint_long_windows(fpe):
+    d = 20_000
+    c = workloads.uniform_coeffs(d, 21)
+    rng = np.random.default_rng(63)
+    z = 2.0 ** rng.uniform(-0.02, 0.02, 3000) * np.exp(1j * rng.uniform(0, 2 * np.pi, 3000))
+    check(fpe, c, z, scaled_g(c, z, 64), "near the unit circle d=20000")
+
+
+def test_adjoint_window_starts_across_chunks(fpe):
+    d = 60_000
+    c = workloads.uniform_coeffs(d, 22)
+    rng = np.random.default_rng(8)
+    lam = np.concatenate([rng.uniform(0.002, 0.016, 768), -rng.uniform(0.002, 0.016, 768)])
+    z = 2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, lam.size))
+    check(fpe, c, z, scaled_g(c, z, 65), "sparse lambda d=60000")
+
+
+@pytest.mark.parametrize("kind", ["wide", "sparse_wide"])
+def test_adjoint_wide_dynamic_range(fpe, kind):
+    gen = workloads.wide_coeffs if kind == "wide" else workloads.sparse_wide_coeffs
+    c = gen(1 << 16, 31)
+    z = workloads.spherical_points(3000, 32)
+    check(fpe, c, z, scaled_g(c, z, 66), kind)
+
+
+def test_adjoint_full_size_sample(fpe):
+    """d = 10^6 and its 10^6 points, in the launch configuration of the
+    benchmark; g is nonzero on 96 sampled points (every other point adds exact
+    zeros), so the oracle sums those points alone."""
+    wl = workloads.workload("uniform_d1e6")
+    rng = np.random.default_rng(67)
+    lam = np.log2(np.abs(wl.points))
+    inside = np.flatnonzero(lam < -0.01)
+    near = np.flatnonzero((np.abs(lam) > 2e-4) & (np.abs(lam) < 1e-3))
+    idx = np.concatenate([rng.choice(inside, 64, replace=False), rng.choice(near, 32, replace=False)])
+    gs = scaled_g(wl.coeffs, wl.points[idx], 68)
+    assert (gs != 0).all()
+    g = np.zeros(len(wl.points), np.complex128)
+    g[idx] = gs
+    plan = fpe.precondition(to_dev(wl.coeffs), 53)
+    ga, gz = plan.adjoint(to_dev(wl.points), to_dev(g))
+    torch.cuda.synchronize()
+    ga, gz = ga.cpu().numpy(), gz.cpu().numpy()
+    ref = oracle.precondition(wl.coeffs, 53).adjoint(wl.points[idx], gs)
+    S = np.ldexp(ref["ga_scale_m"], np.clip(ref["ga_scale_e"], -3000, 3000))
+    want = xval(ref["ga_m"], ref["ga_e"])
+    assert (ga[S == 0] == 0).all()
+    ok = (S >= 2.0 ** -1000) & (S <= 2.0 ** 1000)
+    err = np.abs(ga[ok] - want[ok]) / S[ok]
+    say(f"  d=1e6: grad_a max scaled error {err.max():.3e} on {ok.sum()} coefficients")
+    assert err.max() <= tol_grad_a(96)
+    assert (gz[np.setdiff1d(np.arange(len(g)), idx)] == 0).all()
+
+
+def test_adjoint_edge_cases(fpe):
+    c = workloads.uniform_coeffs(300, 71)
+    plan = fpe.precondition(to_dev(c), 53)
+    # no points: grad_a is cleared
+    ga, gz = plan.adjoint(to_dev(np.zeros(0, np.complex128)), to_dev(np.zeros(0, np.complex128)))
+    assert (ga.cpu().numpy() == 0).all() and gz.numel() == 0
+    # one side only, and agreement with the two-sided call
+    z = workloads.spherical_points(500, 72)
+    g = scaled_g(c, z, 73)
+    ga2, gz2 = plan.adjoint(to_dev(z), to_dev(g))
+    ga1, none = plan.adjoint(to_dev(z), to_dev(g), grad_z=False)
+    none2, gz1 = plan.adjoint(to_dev(z), to_dev(g), grad_a=False)
+    assert none is None and none2 is None
+    assert np.array_equal(gz1.cpu().numpy(), gz2.cpu().numpy())
+    d1, d2 = ga1.cpu().numpy(), ga2.cpu().numpy()
+    assert np.allclose(d1, d2, rtol=0, atol=tol_grad_a(8) * np.abs(d2).max())
+    # z = 0 contributes g to grad_a[0]; a_0 = 0 keeps nothing at 0
+    ga0, gz0 = plan.adjoint(to_dev(np.zeros(3, np.complex128)), to_dev(np.array([1 + 1j, 2.0, -0.5j])))
+    ga0 = ga0.cpu().numpy()
+    assert ga0[0] == (1 + 1j) + 2.0 - 0.5j and (ga0[1:] == 0).all() and (gz0.cpu().numpy() == 0).all()
+    c2 = c.copy()
+    c2[0] = 0
+    plan2 = fpe.precondition(to_dev(c2), 53)
+    ga0, _ = plan2.adjoint(to_dev(np.zeros(2, np.complex128)), to_dev(np.array([1.0, 1.0 + 0j])))
+    assert (ga0.cpu().numpy() == 0).all()
+    # P == 0
+    plan3 = fpe.precondition(to_dev(np.zeros(10, np.complex128)), 53)
+    ga3, gz3 = plan3.adjoint(to_dev(z[:50]), to_dev(g[:50]))
+    assert (ga3.cpu().numpy() == 0).all() and (gz3.cpu().numpy() == 0).all()
+    # mismatched lengths are rejected
+    with pytest.raises(Exception):
+        plan.adjoint(to_dev(z), to_dev(g[:10]))
+
+
+def test_autograd_gradcheck(fpe):
+    """torch.autograd.gradcheck of the differentiable evaluation (both inputs
+    complex) where the window keeps every term (d = 24, |z| near 1)."""
+    rng = np.random.default_rng(81)
+    c = to_dev(workloads.uniform_coeffs(24, 82)).requires_grad_(True)
+    z = to_dev(2.0 ** rng.uniform(-0.05, 0.05, 6) * np.exp(1j * rng.uniform(0, 2 * np.pi, 6))).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, x: fpe.fpe_eval(a, x), (c, z), eps=1e-6, atol=1e-7, rtol=1e-5,
+                                    nondet_tol=1e-12)
+
+
+def test_autograd_central_differences_restricted_windows(fpe):
+    """Windows that drop terms (d = 400, |lambda| up to 1/2): the loss
+    L = Re sum_j conj(c_j) Q_j, backpropagated, against central differences of
+    the GPU evaluation in Re and Im of kept coefficients (hull and G_p
+    unchanged by the step, so Q is linear in them) and of the points (windows
+    unchanged by the step)."""
+    d = 400
+    a = workloads.uniform_coeffs(d, 83)
+    rng = np.random.default_rng(84)
+    lam = rng.uniform(-0.5, 0.5, 24)
+    zs = 2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, 24))
+    r0 = oracle.precondition(a, 53).eval(zs)
+    cw = (rng.normal(size=24) + 1j * rng.normal(size=24)) * np.exp2(-r0["e"].astype(float))
+
+    def loss_np(av, zv):
+        q = fpe.fpe_eval(to_dev(av), to_dev(zv)).cpu().numpy()
+        return float(np.sum((np.conj(cw) * q).real))
+
+    at = to_dev(a).requires_grad_(True)
+    zt = to_dev(zs).requires_grad_(True)
+    L = (torch.conj(to_dev(cw)) * fpe.fpe_eval(at, zt)).real.sum()
+    L.backward()
+    ga, gz = at.grad.cpu().numpy(), zt.grad.cpu().numpy()
+    plan = fpe.precondition(to_dev(a), 53)
+    hk, hs, good = plan.export()
+    kept = np.flatnonzero(np.abs(ga) > 0)
+    assert len(kept) > 50
+    top = kept[np.argsort(-np.abs(ga[kept]))[:100]]
+    assert not np.any(ga[~good])
+    checked = 0
+    for k in rng.choice(top, 12, replace=False):
+        h = 2.0 ** -12 * abs(a[k])
+        vals = []
+        for step in (h, -h, 1j * h, -1j * h):
+            ap = a.copy()
+            ap[k] += step
+            p2 = fpe.precondition(to_dev(ap), 53)
+            hk2, hs2, good2 = p2.export()
+            if not (np.array_equal(good2, good) and np.array_equal(hk2, hk) and np.array_equal(hs2, hs)):
+                break
+            vals.append(loss_np(ap, zs))
+        if len(vals) < 4:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+        assert abs(fd - ga[k]) <= 1e-9 * abs(ga[k]) + 1e-12 / h, (k, fd, ga[k])
+        checked += 1
+    assert checked >= 8
+    _, _, _, win0 = plan.eval(to_dev(zs), window=True)
+    win0 = win0.cpu().numpy()
+    checked = 0
+    for j in range(24):
+        h = 1e-7 * abs(zs[j])
+        vals, same = [], True
+        for step in (h, -h, 1j * h, -1j * h):
+            zp = zs.copy()
+            zp[j] += step
+            _, _, _, wp = plan.eval(to_dev(zp), window=True)
+            same &= bool(np.array_equal(wp.cpu().numpy()[j], win0[j]))
+            vals.append(loss_np(a, zp))
+        if not same:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+        assert abs(fd - gz[j]) <= 1e-6 * abs(gz[j]) + 1e-8 / abs(zs[j]), (j, fd, gz[j])
+        checked += 1
+    assert checked >= 16

@@ -621,3 +621,153 @@ def test_newton_step_paper_example():
     assert q == 10.0 ** 64 and qd == 64 * 10.0 ** 63
     step = (rd["m"][0] / rd["md"][0]) * 2.0 ** (int(rd["e"][0]) - int(rd["ed"][0]))
     assert 10.0 - (10.0 - step) == 0.15625
+
+
+def _xc(m, e):
+    """(complex mantissa, exponent) -> exact Fraction pair."""
+    sc = Fr(2) ** int(e) if e >= 0 else Fr(1, 2 ** int(-e))
+    return (Fr(float(m.real)) * sc, Fr(float(m.imag)) * sc)
+
+
+def test_adjoint_duality_exact_rational_tiny():
+    """Reverse mode against forward mode, exactly: for any direction delta,
+    sum_k conj(grad_a[k]) delta_k equals sum_j conj(g_j) Q_j(delta), where
+    Q_j(delta) is the exact rational sum of delta_k z_j^k over the kept terms of
+    point j (same window and G_p).  A dropped conjugate, a wrong power or a
+    missed term breaks the identity."""
+    rng = np.random.default_rng(93)
+    for c in _random_tiny_polys(rng, 30):
+        z = _tiny_points(rng, 8)
+        d = len(c) - 1
+        P = oracle.precondition(c, 53)
+        r = P.eval(z)
+        good = P.good()
+        g = rng.normal(size=len(z)) + 1j * rng.normal(size=len(z))
+        delta = rng.normal(size=d + 1) + 1j * rng.normal(size=d + 1)
+        adj = P.adjoint(z, g)
+        lhs = (Fr(0), Fr(0))
+        bound = Fr(0)
+        for k in range(d + 1):
+            gk = _xc(adj["ga_m"][k], adj["ga_e"][k])
+            dk = (Fr(float(delta[k].real)), Fr(float(delta[k].imag)))
+            t = cplx_mul((gk[0], -gk[1]), dk)
+            lhs = (lhs[0] + t[0], lhs[1] + t[1])
+            sk = Fr(float(adj["ga_scale_m"][k])) * (Fr(2) ** int(adj["ga_scale_e"][k]) if adj["ga_scale_e"][k] >= 0
+                                                   else Fr(1, 2 ** int(-adj["ga_scale_e"][k])))
+            # the oracle rounds each grad_a[k] once (double-double inside)
+            bound += Fr(abs(delta[k])) * (Fr(2) ** -52 * (abs(gk[0]) + abs(gk[1])) + Fr(2) ** -95 * sk)
+            if not good[k]:
+                assert adj["ga_m"][k] == 0
+        rhs = (Fr(0), Fr(0))
+        for j, zj in enumerate(z):
+            if not np.isfinite(zj) or r["l"][j] > r["r"][j]:
+                continue
+            ks = [k for k in range(r["l"][j], r["r"][j] + 1) if good[k]]
+            q = exact_sum_subset(delta, zj, ks)
+            t = cplx_mul((Fr(float(g[j].real)), -Fr(float(g[j].imag))), q)
+            rhs = (rhs[0] + t[0], rhs[1] + t[1])
+        diff = abs(lhs[0] - rhs[0]) + abs(lhs[1] - rhs[1])
+        assert diff <= 2 * bound + Fr(1, 2 ** 1000), (c, float(diff), float(bound))
+
+
+def test_adjoint_geometric_series_closed_form():
+    """a_k = 1 with every term kept (|z| near 1, so the window is [0, d]):
+    sum_k grad_a[k] = sum_j g_j (1 - w_j^(d+1)) / (1 - w_j), w_j = conj(z_j),
+    and grad_a[0] = sum_j g_j, in exact rationals."""
+    rng = np.random.default_rng(94)
+    for d in (4, 15, 33):
+        c = np.ones(d + 1, np.complex128)
+        P = oracle.precondition(c, 53)
+        z = 2.0 ** rng.uniform(-0.05, 0.05, 6) * np.exp(1j * rng.uniform(0.3, 6.0, 6))
+        r = P.eval(z)
+        assert (r["l"] == 0).all() and (r["r"] == d).all() and P.good().all()
+        g = rng.normal(size=6) + 1j * rng.normal(size=6)
+        adj = P.adjoint(z, g)
+        tot = (Fr(0), Fr(0))
+        for k in range(d + 1):
+            gk = _xc(adj["ga_m"][k], adj["ga_e"][k])
+            tot = (tot[0] + gk[0], tot[1] + gk[1])
+        ex = (Fr(0), Fr(0))
+        for j in range(6):
+            w = (Fr(float(z[j].real)), -Fr(float(z[j].imag)))
+            wp = (Fr(1), Fr(0))
+            for _ in range(d + 1):
+                wp = cplx_mul(wp, w)
+            num = (1 - wp[0], -wp[1])
+            den = (1 - w[0], -w[1])
+            q = den[0] ** 2 + den[1] ** 2
+            s = ((num[0] * den[0] + num[1] * den[1]) / q, (num[1] * den[0] - num[0] * den[1]) / q)
+            t = cplx_mul((Fr(float(g[j].real)), Fr(float(g[j].imag))), s)
+            ex = (ex[0] + t[0], ex[1] + t[1])
+        err = abs(to_complex(tot) - to_complex(ex))
+        assert err <= 2.0 ** -48 * (d + 1) * np.abs(g).sum(), (d, err)
+        g0 = _xc(adj["ga_m"][0], adj["ga_e"][0])
+        assert to_complex(g0) == complex(sum(Fr(float(x.real)) for x in g), sum(Fr(float(x.imag)) for x in g))
+
+
+def _loss(P, z, cw):
+    """L = Re sum_j conj(c_j) Q_j with c_j = cw_j 2^-e0_j (each point O(1))."""
+    r = P.eval(z)
+    tot = 0.0
+    for j in range(len(z)):
+        v = np.conj(cw[j][0]) * r["m"][j]
+        tot += math.ldexp(v.real, int(r["e"][j] - cw[j][1]))
+    return tot
+
+
+def test_adjoint_central_differences():
+    """Central differences of the oracle's own evaluation in Re and Im of a_k
+    (kept k; the plan's hull and G_p unchanged by the step) and of z (window
+    unchanged by the step) against its reverse mode, with the complex
+    convention grad = dL/dRe + i dL/dIm for L = Re sum_j conj(c_j) Q_j."""
+    rng = np.random.default_rng(95)
+    checked_a = checked_z = 0
+    for c in _random_tiny_polys(rng, 20):
+        d = len(c) - 1
+        P = oracle.precondition(c, 53)
+        good = P.good()
+        hk, hs = P.hull()
+        z = np.array(list(workloads.spherical_points(6, int(rng.integers(1 << 30)))) + [0.9 + 0.3j], np.complex128)
+        r0 = P.eval(z)
+        cw = [(complex(rng.normal(), rng.normal()), int(r0["e"][j])) for j in range(len(z))]
+        g = np.array([math.ldexp(1.0, -e) * w for w, e in cw], np.complex128)
+        adj = P.adjoint(z, g)
+        ga = np.array([math.ldexp(m.real, int(e)) + 1j * math.ldexp(m.imag, int(e))
+                       for m, e in zip(adj["ga_m"], adj["ga_e"])])
+        for k in [k for k in range(d + 1) if good[k]][:3]:
+            h = 2.0 ** -20 * abs(c[k])
+            vals = []
+            for step in (h, -h, 1j * h, -1j * h):
+                cp = c.copy()
+                cp[k] += step
+                Pp = oracle.precondition(cp, 53)
+                hk2, hs2 = Pp.hull()
+                if not (np.array_equal(Pp.good(), good) and np.array_equal(hk2, hk) and np.array_equal(hs2, hs)):
+                    break
+                vals.append(_loss(Pp, z, cw))
+            if len(vals) < 4:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+            scale = sum(abs(w) * math.ldexp(m, int(e - e0)) for (w, e0), m, e in
+                        zip(cw, r0["dwin_m"], r0["dwin_e"]))
+            assert abs(fd - ga[k]) <= 2.0 ** -30 * abs(ga[k]) + 2.0 ** -48 * scale / h, (k, fd, ga[k])
+            checked_a += 1
+        gz = adj["gz_m"] * np.exp2(adj["gz_e"].astype(float))
+        for j, zj in enumerate(z):
+            if not (0.25 < abs(zj) < 4):
+                continue
+            h = 1e-6 * abs(zj)
+            vals, same = [], True
+            for step in (h, -h, 1j * h, -1j * h):
+                rp = P.eval(np.array([zj + step]))
+                same &= rp["l"][0] == r0["l"][j] and rp["r"][0] == r0["r"][j]
+                q = rp["m"][0] * 2.0 ** rp["e"][0]
+                vals.append((np.conj(g[j]) * q).real)
+            if not same:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+            sc = abs(g[j]) * (math.ldexp(adj["gz_scale_m"][j] / abs(g[j]) if g[j] else 0.0, int(adj["gz_scale_e"][j]))
+                              + math.ldexp(r0["dwin_m"][j], int(r0["dwin_e"][j])) / abs(zj))
+            assert abs(fd - gz[j]) <= 1e-6 * sc, (j, zj, fd, gz[j])
+            checked_z += 1
+    assert checked_a >= 20 and checked_z >= 20, (checked_a, checked_z)
