@@ -83,6 +83,43 @@ def recorded_traffic(workload: str):
         return None
 
 
+def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
+    """Derivative, reverse mode and Newton at d = 2^18 with 2^20 points: the
+    forward pass with Q' (fpe_eval_deriv), the backward pass of
+    L = sum_j |Q_j|^2 4^(-e_j) (each point's |Q|^2 normalised by its detached
+    exponent, so that no term overflows; upstream gradient 2 Q_j 4^(-e_j)) with
+    respect to every a_k and z_j (fpe_eval_adjoint), and one Newton step on
+    every point (fpe_newton_step)."""
+    wl = workloads.workload("uniform_d2p18")
+    c = torch.from_numpy(wl.coeffs).to(dev)
+    z = torch.from_numpy(wl.points).to(dev)
+    plan = fpe.precondition(c, 53)
+    m, e, md, ed = plan.eval_deriv(z)
+    g = 2.0 * m * torch.pow(2.0, -e.to(torch.float64))
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    n = len(wl.points)
+    t_fwd = timed(lambda: plan.eval_deriv(z))
+    t_bwd = timed(lambda: plan.adjoint(z, g, md, ed))
+    t_newton = timed(lambda: plan.newton_step(z))
+    log(f"d=2^18, 2^20 points: forward with Q' {t_fwd:.3f} ms, backward {t_bwd:.3f} ms, Newton step {t_newton:.3f} ms")
+    return {"workload": wl.name, "d": wl.degree, "n_points": n, "unit": "points/s",
+            "forward_with_derivative": {"ms": t_fwd, "value": n / (t_fwd * 1e-3)},
+            "backward_grad_a_and_z": {"ms": t_bwd, "value": n / (t_bwd * 1e-3)},
+            "newton_step": {"ms": t_newton, "value": n / (t_newton * 1e-3)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +129,7 @@ def main() -> int:
     ap.add_argument("--horner-steps", type=int, default=2)
     ap.add_argument("--no-horner", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f3", action="store_true", help="skip the derivative / adjoint / Newton leg")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--check-sample", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -217,6 +255,9 @@ def main() -> int:
         res["horner_gpu"] = {"value": n / (hms * 1e-3), "unit": "evaluations/s", "ms_per_step": hms,
                              "max_scaled_err": float(herr.max()), "speedup_fpe": (n / (ms_per_step * 1e-3)) / (n / (hms * 1e-3))}
         log(f"horner {hms:.1f} ms/step, max scaled error {herr.max():.3e}")
+
+    if not args.no_f3:
+        res["adjoint_newton"] = adjoint_leg(fpe, workloads, torch, dev, args.steps)
 
     if not args.no_cpu:
         threads = oracle.default_threads()

@@ -151,11 +151,13 @@ class Plan:
                                   _stream(stream), ctypes.byref(h)))
         self._h = h
         self._eval_ws = {}
+        self._destroy = L.fpe_plan_destroy     # kept: module globals may be gone at exit
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().fpe_plan_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     def info(self) -> PlanInfo:

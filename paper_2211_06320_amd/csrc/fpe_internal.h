@@ -159,10 +159,11 @@ __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, doubl
 }
 
 // w^n (n >= 0) for |Re w|, |Im w| < 1 with max in [1/2, 1): left-to-right binary
-// powering in double-double, renormalised once per bit (a square times w stays
-// within [1/8, 3) of a renormalised value, far from the FP64 range limits).
-// Returns the rounded mantissa and adds the binary exponent to E.  Relative
-// error about (2 log2 n) 2^-100.
+// powering in double-double, renormalised every fourth bit and after the last
+// (from a renormalised value, whose modulus is in [1/2, 2^(1/2)), four
+// squarings with products by w keep the modulus within [2^-31, 2^8], far from
+// the FP64 range limits).  Returns the renormalised, rounded mantissa and adds
+// the binary exponent to E.  Relative error about (2 log2 n) 2^-100.
 __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, double &pr, double &pi,
                                         long long &E) {
     if (n == 0) { pr = 1.0; pi = 0.0; return; }
@@ -173,7 +174,7 @@ __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, do
         x = cdd_sqr(x);
         ex *= 2;                      // squaring doubles the exponent
         if ((n >> b) & 1) x = cdd_mul_d(x, wr, wi);
-        cdd_renorm(x, ex);
+        if ((b & 3) == 0) cdd_renorm(x, ex);
     }
     E += ex;
     pr = x.rh + x.rl;
