@@ -120,6 +120,43 @@ def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
             "newton_step": {"ms": t_newton, "value": n / (t_newton * 1e-3)}}
 
 
+def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> dict:
+    """FP32 window sums at p = 24 (FPE_PRECONDITION_FP32) beside FP64 arithmetic at
+    the same p, on the headline workload and the two wide-range workloads
+    (d = 2^20): evaluations/s over all points and the max scaled error against
+    the oracle at p = 24 on a seeded sample."""
+    out = {}
+    for name in ("uniform_d1e6", "wide_d2p20", "sparse_wide_d2p20"):
+        wl = workloads.workload(name)
+        c = torch.from_numpy(wl.coeffs).to(dev)
+        z = torch.from_numpy(wl.points).to(dev)
+        n = len(wl.points)
+        idx = np.random.default_rng(12346).choice(n, min(check, n), replace=False)
+        ref = oracle.precondition(wl.coeffs, 24).eval(wl.points[idx])
+        row = {"d": wl.degree, "n_points": n}
+        for label, fp32 in (("fp32", True), ("fp64_arith", False)):
+            plan = fpe.precondition(c, 24, fp32=fp32)
+            mo = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+            plan.eval(z, out=mo)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                plan.eval(z, out=mo)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            mm, ee = mo[0].cpu().numpy(), mo[1].cpu().numpy()
+            err = oracle.scaled_error(mm[idx], ee[idx], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+            row[label] = {"ms": ms, "value": n / (ms * 1e-3), "max_scaled_err": float(err.max())}
+        log(f"p=24 {name}: FP32 {row['fp32']['ms']:.3f} ms (max err {row['fp32']['max_scaled_err']:.2e}), "
+            f"FP64 arithmetic {row['fp64_arith']['ms']:.3f} ms (max err {row['fp64_arith']['max_scaled_err']:.2e})")
+        out[name] = row
+    out["unit"] = "evaluations/s"
+    out["tolerance"] = 2.0 ** -18
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +167,7 @@ def main() -> int:
     ap.add_argument("--no-horner", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f3", action="store_true", help="skip the derivative / adjoint / Newton leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 (p = 24) leg")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--check-sample", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -258,6 +296,8 @@ def main() -> int:
 
     if not args.no_f3:
         res["adjoint_newton"] = adjoint_leg(fpe, workloads, torch, dev, args.steps)
+    if not args.no_fp32:
+        res["fp32_p24"] = fp32_leg(fpe, workloads, oracle, np, torch, dev, args.steps, args.check_sample)
 
     if not args.no_cpu:
         threads = oracle.default_threads()

@@ -68,8 +68,26 @@ int32_t fpe_abi_version(void);
 /* Preconditioning (Algorithm A_p, first block; Section 5.1).                */
 /* ------------------------------------------------------------------------- */
 
+/* Precondition flags. */
+enum {
+    /* fpe_eval of this plan sums the windows in FP32 (requires p_bits <= 24):
+     * the coefficients a_k (k in G_p) are also stored as FP32 numbers scaled
+     * per chunk of C coefficients, each tile's window part runs a plain FP32
+     * Horner recurrence over blocks of 8 coefficients, and the block partials
+     * are accumulated in FP64 (Horner in z^8), as are z^l and the sum over
+     * chunks.  A tile falls back to FP64 arithmetic where FP32 cannot hold it:
+     * a chunk whose good coefficients span more than 120 binary orders (or
+     * whose cover drops by more than 99 within the chunk), a wavefront holding
+     * a point with |z| outside [2^-12, 2^12], the ragged start of windows
+     * inside a tile.  Error bound: the FP32 block Horner contributes at most
+     * about 24 2^-24 sum |a_k||z|^k (8 steps, the rounding of z and of a_k);
+     * fpe_eval_deriv, fpe_newton_step and fpe_eval_adjoint stay in FP64. */
+    FPE_PRECONDITION_FP32 = 1u
+};
+
 /* Bytes of device workspace fpe_precondition needs for a polynomial of degree
-   d (d + 1 coefficients) at precision p_bits.  flags: 0 (reserved). */
+   d (d + 1 coefficients) at precision p_bits.  flags: 0 or
+   FPE_PRECONDITION_FP32 (then p_bits <= 24). */
 fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits, uint32_t flags,
                                            size_t *bytes);
 
@@ -83,15 +101,17 @@ fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits, uint32_t f
  *   d               degree as given, 0 <= d < 2^31 - 1.  Zero coefficients at
  *                   either end are trimmed (the paper assumes a_0 != 0 and
  *                   a_d != 0, Section 4.3), so s(d) uses the trimmed degree.
- *   p_bits          1..53: the precision p of the truncation rule (53 = FP64).
- *   flags           0 (reserved).
+ *   p_bits          1..53: the precision p of the truncation rule (53 = FP64,
+ *                   24 = FP32).
+ *   flags           0, or FPE_PRECONDITION_FP32 (p_bits <= 24; FP32 window sums).
  *   workspace_dev   device buffer of at least the queried size, 256-byte aligned;
  *                   owned by the caller, borrowed by the plan.
  *   stream          HIP stream the work is enqueued on; the call waits for it.
  *   out_plan        receives the handle (free it with fpe_plan_destroy).
  *
  * Errors: FPE_ERR_INVALID_ARG (NULL pointer, d out of range, misaligned
- * workspace), FPE_ERR_PRECISION, FPE_ERR_WORKSPACE, FPE_ERR_NONFINITE (a NaN or
+ * workspace, unknown flag), FPE_ERR_PRECISION (p_bits outside 1..53, or above
+ * 24 with FPE_PRECONDITION_FP32), FPE_ERR_WORKSPACE, FPE_ERR_NONFINITE (a NaN or
  * infinite coefficient), FPE_ERR_UNSUPPORTED (the scales of the good
  * coefficients span more binary orders of magnitude than an FP64 window sum can
  * hold: max s - min good s > 2 (958 - T)), FPE_ERR_HIP.  An all-zero polynomial

@@ -6,6 +6,7 @@ memory (all buffers, including workspaces, are torch tensors) and the stream.
 There is no fallback: if libfpe.so is missing, loading fails with an error.
 
     plan = precondition(coeffs)            # coeffs: complex128 CUDA tensor, a_0 first
+    plan32 = precondition(coeffs, 24, fp32=True)   # FP32 window sums at p = 24
     m, e = plan.eval(z)                    # P(z) ~ m * 2**e, m complex128, e int64
     m, e, terms, window = plan.eval(z, terms=True, window=True)
     m, e = horner_eval(coeffs, z)          # same-GPU Horner baseline
@@ -26,6 +27,7 @@ LIB_PATH = os.path.join(HERE, "libfpe.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fpe.h")
 
 FPE_OK = 0
+PRECONDITION_FP32 = 1
 STATUS = {0: "FPE_OK", 1: "FPE_ERR_INVALID_ARG", 2: "FPE_ERR_NONFINITE", 3: "FPE_ERR_PRECISION",
           4: "FPE_ERR_WORKSPACE", 5: "FPE_ERR_HIP", 6: "FPE_ERR_UNSUPPORTED"}
 
@@ -138,16 +140,18 @@ class PlanInfo:
 class Plan:
     """A polynomial preconditioned by fpe_precondition (Algorithm A_p, first block)."""
 
-    def __init__(self, coeffs, p: int = 53, stream=None):
+    def __init__(self, coeffs, p: int = 53, stream=None, fp32: bool = False):
         L = lib()
         coeffs = _dev_complex(coeffs, "coeffs")
         self.device = coeffs.device
         self.d = coeffs.shape[0] - 1
+        self.fp32 = bool(fp32)
+        flags = PRECONDITION_FP32 if fp32 else 0
         nb = ctypes.c_size_t()
-        _check(L.fpe_precondition_workspace_size(self.d, p, 0, ctypes.byref(nb)))
+        _check(L.fpe_precondition_workspace_size(self.d, p, flags, ctypes.byref(nb)))
         self._ws_buf, ws = _workspace(nb.value, coeffs.device)
         h = ctypes.c_void_p()
-        _check(L.fpe_precondition(coeffs.data_ptr(), self.d, p, 0, ws, nb.value,
+        _check(L.fpe_precondition(coeffs.data_ptr(), self.d, p, flags, ws, nb.value,
                                   _stream(stream), ctypes.byref(h)))
         self._h = h
         self._eval_ws = {}
@@ -316,8 +320,9 @@ def fpe_eval(coeffs, z, p: int = 53):
     return _FPE_FN.apply(_dev_complex(coeffs, "coeffs"), _dev_complex(z, "z"), p)
 
 
-def precondition(coeffs, p: int = 53, stream=None) -> Plan:
-    return Plan(coeffs, p, stream)
+def precondition(coeffs, p: int = 53, stream=None, fp32: bool = False) -> Plan:
+    """fp32=True (p <= 24): fpe_eval sums the windows in FP32 (FPE_PRECONDITION_FP32)."""
+    return Plan(coeffs, p, stream, fp32)
 
 
 def horner_eval(coeffs, z, out=None, stream=None):

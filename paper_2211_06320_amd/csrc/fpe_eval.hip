@@ -658,6 +658,65 @@ __device__ __forceinline__ void run_steps(Acc<D> &a, double zr, double zi, const
     for (; k >= kto; --k) masked_step<M>(a, zr, zi, cf[2 * k], cf[2 * k + 1], k, lo, hi);
 }
 
+// ---- FP32 window sums (plans with FP32 tables)
+constexpr int kBlock32 = 8;   // coefficients per FP32 block: one 64-byte scalar load of float2
+
+// one FP32 Horner step h <- h z + a (four FMAs, each rounded to FP32)
+__device__ __forceinline__ void step32(float &hr, float &hi, float zr, float zi, float ar, float ai) {
+    const float tr = fmaf(-hi, zi, ar), ti = fmaf(hr, zi, ai);
+    hr = fmaf(hr, zr, tr);
+    hi = fmaf(hi, zr, ti);
+}
+
+// H = sum over k = kto .. min(hi, kfrom) of a_k z^(k - kto), for the common and
+// top parts [kto, kfrom] of a tile (every active lane has lo <= kto): the
+// FP32 table in blocks of kBlock32 coefficients from the top, each block by a
+// plain FP32 Horner recurrence in z (lanes with hi below a coefficient add 0,
+// so their recurrence stays 0 until their part starts), and the block partials
+// by an FP64 Horner recurrence in z^8.  ktop: above it every lane takes every
+// step.  Returns H in the FP64 table's scale (times 2^sg).
+__device__ __forceinline__ void run_f32(double &Hr, double &Hi, float zr, float zi, double z8r, double z8i,
+                                        const_table32_t c32, int sg, int kfrom, int kto, int ktop, int hi) {
+    FPE_NO_CONTRACT
+    const int len = kfrom - kto + 1;
+    const int l0 = len % kBlock32;
+    Hr = 0.0;
+    Hi = 0.0;
+    int k = kfrom;
+    if (l0 > 0) {                              // the short block at the top
+        float hr = 0.0f, hh = 0.0f;
+        for (int j = 0; j < l0; ++j, --k) {
+            const float ar = c32[2 * k], ai = c32[2 * k + 1];
+            const bool on = k <= hi;
+            step32(hr, hh, zr, zi, on ? ar : 0.0f, on ? ai : 0.0f);
+        }
+        Hr = (double)hr;
+        Hi = (double)hh;
+    }
+    for (; k >= kto; k -= kBlock32) {          // full blocks [k - 7, k]
+        const_table32_t p = c32 + 2 * (k - kBlock32 + 1);
+        float A[2 * kBlock32];
+#pragma unroll
+        for (int q = 0; q < 2 * kBlock32; ++q) A[q] = p[q];
+        float hr = 0.0f, hh = 0.0f;
+        if (k > ktop) {
+#pragma unroll
+            for (int s2 = kBlock32 - 1; s2 >= 0; --s2) {
+                const bool on = k - (kBlock32 - 1 - s2) <= hi;
+                step32(hr, hh, zr, zi, on ? A[2 * s2] : 0.0f, on ? A[2 * s2 + 1] : 0.0f);
+            }
+        } else {
+#pragma unroll
+            for (int s2 = kBlock32 - 1; s2 >= 0; --s2) step32(hr, hh, zr, zi, A[2 * s2], A[2 * s2 + 1]);
+        }
+        const double nr = fma(Hr, z8r, fma(-Hi, z8i, (double)hr));
+        Hi = fma(Hr, z8i, fma(Hi, z8r, (double)hh));
+        Hr = nr;
+    }
+    Hr = ldexp(Hr, sg);
+    Hi = ldexp(Hi, sg);
+}
+
 constexpr int kWindowThreads = 256;
 constexpr int kWindowWaves = kWindowThreads / kWave;
 
@@ -817,6 +876,21 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
         PowState pw;                                      // chained powers of this segment
         for (int k = 0; k < kAccWords; ++k) s_acc[k][threadIdx.x] = 0;
+        // FP32 tiles: z in FP32 (|z| in [2^-12, 2^12]) and z^8 in FP64
+        const bool z32ok = !valid || (ez >= -11 && ez <= 12);
+        const float zr32 = (float)ldexp(wr, ez), zi32 = (float)ldexp(wi, ez);
+        double z8r = 0.0, z8i = 0.0;
+        if (!D && P.coef32) {
+            FPE_NO_CONTRACT
+            double ar = ldexp(wr, ez), ai = ldexp(wi, ez);
+            for (int q = 0; q < 3; ++q) {
+                const double nr = fma(ar, ar, -(ai * ai));
+                ai = 2.0 * ar * ai;
+                ar = nr;
+            }
+            z8r = ar;
+            z8i = ai;
+        }
         for (;;) {
             // ---- tile (g, c): this lane's part [lo, hi] of chunk c
             const int c0 = c * C, c1 = c0 + C - 1;
@@ -835,12 +909,28 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 tile_power(pw, l, lo, act, c, C, wr, wi, s_ch, s_che, t, pr, pi, pe);
                 Acc<D> acc;
                 const double zr = ldexp(wr, ez), zi = ldexp(wi, ez);
-                if (Ahi >= Alo) {
-                    run_steps<kTop>(acc, zr, zi, cf, Khi, Ahi + 1, lo, hi);
-                    run_steps<kAll>(acc, zr, zi, cf, Ahi, Alo, lo, hi);
-                    run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
-                } else {
-                    run_steps<kBoth>(acc, zr, zi, cf, Khi, Klo, lo, hi);
+                // FP32 for the common and top parts where the chunk and every
+                // active lane's |z| allow it, then the ragged bottom in FP64
+                bool f32 = false;
+                if constexpr (!D) {
+                    if (P.coef32 && Ahi >= Alo) {
+                        const int sg = __builtin_amdgcn_readfirstlane(P.sig32[c]);
+                        f32 = sg != kNoFp32 && __ballot(act && !z32ok) == 0;
+                        if (f32) {
+                            run_f32(acc.hr, acc.hi, zr32, zi32, z8r, z8i, (const_table32_t)P.coef32, sg, Khi, Alo,
+                                    Ahi, hi);
+                            run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
+                        }
+                    }
+                }
+                if (!f32) {
+                    if (Ahi >= Alo) {
+                        run_steps<kTop>(acc, zr, zi, cf, Khi, Ahi + 1, lo, hi);
+                        run_steps<kAll>(acc, zr, zi, cf, Ahi, Alo, lo, hi);
+                        run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
+                    } else {
+                        run_steps<kBoth>(acc, zr, zi, cf, Khi, Klo, lo, hi);
+                    }
                 }
                 if (act) {
                     // times z^lo = (pr + i pi) 2^(pe + lo ez)

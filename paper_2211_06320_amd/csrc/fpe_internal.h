@@ -34,7 +34,13 @@ struct DevPlan {
     int32_t fix_lo;           // extra bits of their low word
     int32_t coef_shift;       // coef holds a_k 2^-coef_shift (keeps window sums in range)
     double2 a0;               // a_0, returned at z = 0
+    // FP32 window sums (FPE_PRECONDITION_FP32), else both NULL: coef32[k] =
+    // coef[k] 2^-sig32[c] as FP32, c = k / chunk; sig32[c] = kNoFp32 where a
+    // chunk's tiles stay in FP64
+    const float2 *coef32;
+    const int32_t *sig32;
 };
+constexpr int32_t kNoFp32 = INT32_MIN;
 
 // What the window kernel needs of one point: z, its window [l, r] and the
 // reference exponent eref (every kept term is below 2^eref in magnitude).
@@ -78,6 +84,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
 #define FPE_CONST_AS
 #endif
 typedef const FPE_CONST_AS double *const_table_t;
+typedef const FPE_CONST_AS float *const_table32_t;
 
 // ---------------------------------------------------------------- device math
 // The error-free transforms below (TwoSum, TwoProd through fma) rely on every

@@ -27,9 +27,13 @@ struct PreWs {
     double *hull_k;    // d + 1
     double *hull_s;    // d + 1
     int32_t *flags;    // [0] non-finite coefficient seen
+    float2 *coef32;    // d + 1 (FP32 plans): coef 2^-sig32[chunk] as FP32
+    int32_t *sig32;    // chunks (FP32 plans)
 };
 
-size_t pre_layout(int64_t d, PreWs *w, void *base) {
+int64_t n_chunks(int64_t d) { return d / kChunk + 1; }
+
+size_t pre_layout(int64_t d, uint32_t pflags, PreWs *w, void *base) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
@@ -40,7 +44,13 @@ size_t pre_layout(int64_t d, PreWs *w, void *base) {
     double *hk = (double *)take(sizeof(double) * n1);
     double *hs = (double *)take(sizeof(double) * n1);
     int32_t *flags = (int32_t *)take(sizeof(int32_t) * 64);
-    if (w) *w = {scales, coef, gprefix, hk, hs, flags};
+    float2 *coef32 = nullptr;
+    int32_t *sig32 = nullptr;
+    if (pflags & FPE_PRECONDITION_FP32) {
+        coef32 = (float2 *)take(sizeof(float2) * n1);
+        sig32 = (int32_t *)take(sizeof(int32_t) * n_chunks(d));
+    }
+    if (w) *w = {scales, coef, gprefix, hk, hs, flags, coef32, sig32};
     return off;
 }
 
@@ -97,6 +107,21 @@ __global__ void k_mask(const double2 *__restrict__ coef, const int32_t *__restri
     out[k] = o;
 }
 
+// the FP32 table: coef32[k] = coef[k] 2^-sig32[k / C] rounded to FP32 (0 in
+// chunks that stay in FP64)
+__global__ void k_mask32(const double2 *__restrict__ coef, const int32_t *__restrict__ sig32, int64_t n,
+                         float2 *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t sg = sig32[k / kChunk];
+    float2 o = make_float2(0.0f, 0.0f);
+    if (sg != kNoFp32) {
+        const double2 a = coef[k];
+        o = make_float2((float)ldexp(a.x, -sg), (float)ldexp(a.y, -sg));
+    }
+    out[k] = o;
+}
+
 int64_t bitlen(int64_t v) {
     int64_t b = 0;
     while (v > 0) { ++b; v >>= 1; }
@@ -113,8 +138,10 @@ extern "C" fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits,
     if (!bytes) return fail(FPE_ERR_INVALID_ARG, "bytes is NULL");
     if (d < 0 || d >= INT32_MAX - 2) return fail(FPE_ERR_INVALID_ARG, "degree out of range");
     if (p_bits < 1 || p_bits > 53) return fail(FPE_ERR_PRECISION, "p_bits must be in 1..53");
-    if (flags != 0) return fail(FPE_ERR_INVALID_ARG, "flags must be 0");
-    *bytes = pre_layout(d, nullptr, nullptr);
+    if (flags & ~(uint32_t)FPE_PRECONDITION_FP32) return fail(FPE_ERR_INVALID_ARG, "unknown flag");
+    if ((flags & FPE_PRECONDITION_FP32) && p_bits > 24)
+        return fail(FPE_ERR_PRECISION, "FP32 window sums need p_bits <= 24");
+    *bytes = pre_layout(d, flags, nullptr, nullptr);
     set_error("");
     return FPE_OK;
 }
@@ -134,7 +161,7 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
         return fail(FPE_ERR_INVALID_ARG, "workspace must be 256-byte aligned, coefficients 16-byte aligned");
 
     PreWs w;
-    pre_layout(d, &w, workspace_dev);
+    pre_layout(d, flags, &w, workspace_dev);
     const int64_t n1 = d + 1;
     const double2 *coef = reinterpret_cast<const double2 *>(coef_dev);
     const int threads = 256;
@@ -167,6 +194,7 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     std::vector<int32_t> goodflag(n1, 0);
     std::vector<int32_t> prefix(n1 + 1, 0);
     std::vector<double> hk, hs;
+    std::vector<int32_t> sig32;
     int64_t shift = 0;
     if (v >= n1) {  // P == 0
         plan->v = -1; plan->dt = -1; plan->nh = 0; plan->ngood = 0; plan->T = 0;
@@ -219,6 +247,33 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
             return fail(FPE_ERR_UNSUPPORTED, "good coefficients span too many binary orders for FP64 windows");
         }
         for (int64_t k = 0; k < n1; ++k) prefix[k + 1] = prefix[k] + goodflag[k];
+        if (flags & FPE_PRECONDITION_FP32) {
+            // per chunk: sigma = the largest good scale (FP32 entries below 1 in
+            // modulus), FP32 only if every good entry stays a normal FP32
+            // number with margin (sigma - min good s <= 120) and the cover drops
+            // by at most 99 within the chunk (then a block partial of any point
+            // that matters stays above the FP32 range floor)
+            const int64_t nch = n_chunks(d);
+            sig32.assign(nch, kNoFp32);
+            auto ehat = [&](int64_t k) {        // the cover at k in [v, dt]
+                if (ck.size() == 1) return (double)cs[0];
+                size_t i = std::upper_bound(ck.begin(), ck.end(), k) - ck.begin();
+                if (i == 0) i = 1;
+                if (i >= ck.size()) i = ck.size() - 1;
+                const double k0 = (double)ck[i - 1], k1 = (double)ck[i];
+                return (double)cs[i - 1] + (double)(cs[i] - cs[i - 1]) * ((double)k - k0) / (k1 - k0);
+            };
+            for (int64_t c = 0; c < nch; ++c) {
+                const int64_t a = std::max<int64_t>(c * kChunk, v), b = std::min<int64_t>(c * kChunk + kChunk - 1, dt);
+                if (a > b) { sig32[c] = 0; continue; }          // no coefficient of the trimmed range
+                int64_t gmax = INT64_MIN, gmin = INT64_MAX;
+                for (int64_t k = a; k <= b; ++k)
+                    if (goodflag[k]) { gmax = std::max<int64_t>(gmax, s[k]); gmin = std::min<int64_t>(gmin, s[k]); }
+                if (gmax == INT64_MIN) { sig32[c] = 0; continue; }   // no good coefficient: entries 0
+                const double emin = std::min(ehat(a), ehat(b));      // concave: least at an end
+                if (gmax - gmin <= 120 && (double)gmax - emin <= 99.0) sig32[c] = (int32_t)(gmax - shift);
+            }
+        }
         hk.assign(ck.begin(), ck.end());
         hs.assign(cs.begin(), cs.end());
         plan->v = v; plan->dt = dt; plan->nh = (int64_t)ck.size(); plan->ngood = ngood; plan->T = T;
@@ -235,6 +290,13 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     FPE_HIP_CHECK(hipMemcpyAsync(w.scales, goodflag.data(), sizeof(int32_t) * n1, hipMemcpyHostToDevice, stream));
     k_mask<<<blocks, threads, 0, stream>>>(coef, w.scales, n1, (int)shift, w.coef);
     FPE_HIP_CHECK(hipGetLastError());
+    if (flags & FPE_PRECONDITION_FP32) {
+        if (sig32.empty()) sig32.assign(n_chunks(d), kNoFp32);      // P == 0
+        FPE_HIP_CHECK(hipMemcpyAsync(w.sig32, sig32.data(), sizeof(int32_t) * sig32.size(), hipMemcpyHostToDevice,
+                                     stream));
+        k_mask32<<<blocks, threads, 0, stream>>>(w.coef, w.sig32, n1, w.coef32);
+        FPE_HIP_CHECK(hipGetLastError());
+    }
     FPE_HIP_CHECK(hipStreamSynchronize(stream));
 
     DevPlan &P = plan->dev;
@@ -257,6 +319,8 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     P.fix_lo = (int32_t)std::min<int64_t>(44, 62 - bitlen(chunks));
     P.coef_shift = (int32_t)shift;
     P.a0 = a0;
+    P.coef32 = (flags & FPE_PRECONDITION_FP32) ? w.coef32 : nullptr;
+    P.sig32 = (flags & FPE_PRECONDITION_FP32) ? w.sig32 : nullptr;
     *out_plan = plan.release();
     set_error("");
     return FPE_OK;

@@ -43,6 +43,13 @@ def test_workspace_size_queries_validate():
     assert L.fpe_precondition_workspace_size(10, 0, 0, ctypes.byref(b)) == 3
     assert L.fpe_precondition_workspace_size(10, 53, 7, ctypes.byref(b)) == 1
     assert L.fpe_precondition_workspace_size(10, 53, 0, None) == 1
+    # FP32 window sums: p <= 24 only, and room for the FP32 table and chunk scales
+    assert L.fpe_precondition_workspace_size(1000, 53, fpe.PRECONDITION_FP32, ctypes.byref(b)) == 3
+    assert L.fpe_precondition_workspace_size(1000, 24, 0, ctypes.byref(b)) == fpe.FPE_OK
+    plain = b.value
+    assert L.fpe_precondition_workspace_size(1000, 24, fpe.PRECONDITION_FP32, ctypes.byref(b)) == fpe.FPE_OK
+    assert b.value >= plain + 1001 * 8 + 4 * (1000 // 512 + 1)
+    assert L.fpe_precondition_workspace_size(1000, 24, 2, ctypes.byref(b)) == 1
 
 
 def test_null_arguments_rejected_without_gpu_work():
@@ -51,5 +58,6 @@ def test_null_arguments_rejected_without_gpu_work():
     assert L.fpe_precondition(None, 10, 53, 0, None, 0, None, ctypes.byref(h)) == 1
     assert L.fpe_eval(None, None, 0, None, None, None, None, None, 0, None) == 1
     assert L.fpe_horner_eval(None, -1, None, 0, None, None, None) == 1
+    assert L.fpe_eval_adjoint(None, None, 0, None, None, None, None, None, None, 0, None) == 1
     assert L.fpe_plan_info(None, None) == 1
     assert L.fpe_plan_destroy(None) == 0
