@@ -231,6 +231,58 @@ fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, con
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Many polynomials in one evaluation (Algorithm A_p, second block, applied  */
+/* to each polynomial of a batch with its own points; Section 5.2).          */
+/* ------------------------------------------------------------------------- */
+
+/* Opaque handle: the device tables of a batch (a plan per polynomial and the
+ * layout of its points), built once, then evaluated any number of times. */
+typedef struct fpe_batch_s *fpe_batch_t;
+
+/* Bytes of device workspace fpe_batch_create needs for n_poly polynomials whose
+ * points are laid out by z_offsets_host (n_poly + 1 host int64: polynomial i
+ * owns points z_offsets[i] .. z_offsets[i+1] - 1, z_offsets[0] == 0).
+ * Errors: FPE_ERR_INVALID_ARG (NULL, n_poly < 1, offsets not starting at 0 or
+ * decreasing, 2^31 points or more), FPE_ERR_UNSUPPORTED (a polynomial with
+ * more than 4096 points: evaluate it with fpe_eval). */
+fpe_status fpe_batch_workspace_size(int32_t n_poly, const int64_t *z_offsets_host, size_t *bytes);
+
+/* Builds a batch from n_poly plans (host array of handles, all on one device;
+ * a plan may appear more than once) and the point layout z_offsets_host.  The
+ * batch copies the plans' device views (their workspaces must outlive it) into
+ * workspace_dev (caller-owned, 256-byte aligned, at least the queried size),
+ * on stream; the call waits for the copies.  Errors as
+ * fpe_batch_workspace_size, plus FPE_ERR_WORKSPACE and FPE_ERR_HIP. */
+fpe_status fpe_batch_create(const fpe_plan_t *plans_host, int32_t n_poly, const int64_t *z_offsets_host,
+                            void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                            fpe_batch_t *out_batch);
+
+/* Releases the host handle (the workspace stays the caller's). */
+fpe_status fpe_batch_destroy(fpe_batch_t batch);
+
+/* Bytes of device workspace one fpe_eval_batched call needs. */
+fpe_status fpe_eval_batched_workspace_size(fpe_batch_t batch, size_t *bytes);
+
+/* Q_lambda(z_j) of polynomial i at each of its points, for every polynomial of
+ * the batch, as fpe_eval would give it: one launch sequence for the whole batch
+ * (a workgroup per polynomial computes its points' windows and sorts them by
+ * lambda; the (point group, chunk) tiles of all polynomials are then split
+ * evenly over the resident wavefronts).  Enqueues kernels only (no host
+ * synchronisation, no allocation), so a HIP graph can capture it.
+ *
+ *   z_dev          2 N doubles, N = z_offsets[n_poly], in the batch's layout.
+ *   m_dev, e_dev   outputs, as fpe_eval (input order).
+ *   terms_dev      optional n int32 kept-term counts (NULL to skip).
+ *   workspace_dev  at least fpe_eval_batched_workspace_size bytes, 256-byte
+ *                  aligned; one call at a time per workspace.
+ *
+ * With FP64 plans the results are bit for bit those of fpe_eval on each plan
+ * alone.  Errors: FPE_ERR_INVALID_ARG, FPE_ERR_WORKSPACE, FPE_ERR_HIP. */
+fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, double *m_dev, int64_t *e_dev,
+                            int32_t *terms_dev, void *workspace_dev, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Same-GPU baseline: Horner's rule on the full polynomial (Section 1).      */
 /* ------------------------------------------------------------------------- */
 

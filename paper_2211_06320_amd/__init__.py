@@ -14,6 +14,7 @@ There is no fallback: if libfpe.so is missing, loading fails with an error.
     m, e, md, ed = plan.eval_deriv(z)      # and Q' = md * 2**ed through the same window
     ga, gz = plan.adjoint(z, g)            # reverse mode for upstream gradients g
     q = fpe_eval(coeffs, z)                # differentiable (torch.autograd)
+    b = Batch([plan_a, plan_b], [0, na, na + nb]); m, e = b.eval(z_ab)   # many polynomials at once
 """
 from __future__ import annotations
 
@@ -80,6 +81,16 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_deriv.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_newton_step.restype = i32
     L.fpe_newton_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_batch_workspace_size.restype = i32
+    L.fpe_batch_workspace_size.argtypes = [i32, P(i64), P(sz)]
+    L.fpe_batch_create.restype = i32
+    L.fpe_batch_create.argtypes = [P(vp), i32, P(i64), vp, sz, vp, P(vp)]
+    L.fpe_batch_destroy.restype = i32
+    L.fpe_batch_destroy.argtypes = [vp]
+    L.fpe_eval_batched_workspace_size.restype = i32
+    L.fpe_eval_batched_workspace_size.argtypes = [vp, P(sz)]
+    L.fpe_eval_batched.restype = i32
+    L.fpe_eval_batched.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_eval_adjoint.restype = i32
     L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_horner_eval.restype = i32
@@ -277,6 +288,61 @@ class Plan:
                                       ga.data_ptr() if ga is not None else None,
                                       gz.data_ptr() if gz is not None else None, ws, nb, _stream(stream)))
         return ga, gz
+
+
+class Batch:
+    """Many polynomials, each with its own points, evaluated by one launch
+    sequence (fpe_eval_batched).  plans: Plan objects (kept alive by the batch);
+    offsets: n_poly + 1 integers, polynomial i owns points offsets[i] ..
+    offsets[i+1] - 1 of the concatenated point array."""
+
+    def __init__(self, plans, offsets, stream=None):
+        L = lib()
+        self.plans = list(plans)
+        offs = [int(x) for x in offsets]
+        n_poly = len(self.plans)
+        if len(offs) != n_poly + 1:
+            raise ValueError("offsets must have len(plans) + 1 entries")
+        self.n_points = offs[-1]
+        self.device = self.plans[0].device
+        c_offs = (ctypes.c_int64 * len(offs))(*offs)
+        nb = ctypes.c_size_t()
+        _check(L.fpe_batch_workspace_size(n_poly, c_offs, ctypes.byref(nb)))
+        self._ws_buf, ws = _workspace(nb.value, self.device)
+        handles = (ctypes.c_void_p * n_poly)(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(L.fpe_batch_create(handles, n_poly, c_offs, ws, nb.value, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._destroy = L.fpe_batch_destroy
+        enb = ctypes.c_size_t()
+        _check(L.fpe_eval_batched_workspace_size(h, ctypes.byref(enb)))
+        self._eval_buf, self._eval_ws = _workspace(enb.value, self.device)
+        self._eval_nb = enb.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            self._h = None
+
+    def eval(self, z, terms: bool = False, out=None, stream=None):
+        """Q_lambda at every point of every polynomial: (m, e) or (m, e, terms)."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        if z.shape[0] != self.n_points:
+            raise ValueError(f"expected {self.n_points} points")
+        n = self.n_points
+        if out is None:
+            m = torch.empty(n, dtype=torch.complex128, device=z.device)
+            e = torch.empty(n, dtype=torch.int64, device=z.device)
+        else:
+            m, e = out
+        t = torch.empty(n, dtype=torch.int32, device=z.device) if terms else None
+        _check(lib().fpe_eval_batched(self._h, z.data_ptr(), m.data_ptr(), e.data_ptr(),
+                                      t.data_ptr() if t is not None else None, self._eval_ws, self._eval_nb,
+                                      _stream(stream)))
+        return (m, e, t) if terms else (m, e)
 
 
 def _fpe_function():

@@ -37,7 +37,9 @@
 // |z| and evaluating points of similar size together (Section 1; Section 8.1
 // on parallelisation); here the order is what lets a wavefront read one
 // coefficient per step for all of its lanes.
+#include <algorithm>
 #include <climits>
+#include <memory>
 #include <utility>
 #include <vector>
 
@@ -79,6 +81,7 @@ __device__ __forceinline__ void normalise(double re, double im, long long E, dou
 
 // global exclusive prefix of the finished-points bin = number of points with a window
 __device__ __forceinline__ int valid_points(const EvalWs &W) {
+    if (W.n_slots >= 0) return (int)W.n_slots;      // a batch: every slot, padding included
     const int64_t idx = (int64_t)kBins * W.n_sort_blocks;
     return W.tscan[idx] + W.bin_off[kBins / W.tab_ib];
 }
@@ -398,6 +401,78 @@ __device__ __forceinline__ long long group_total(const GroupCost &gc) {
 
 constexpr int kGroupsPerBlock = 1024 / kWave;
 
+// ---- many polynomials in one evaluation (fpe_eval_batched)
+constexpr int kBatchMaxPoints = 4096;   // points of one polynomial of a batch (sorted by one workgroup)
+constexpr int kBatchThreads = 1024;
+
+// One workgroup per polynomial of a batch: the bounds of its points (as in
+// k_bounds, with its own cover in LDS), their order by lambda bin (a bitonic
+// sort in LDS of bin x kBatchMaxPoints + index; finished points have the bin
+// kBins and come last) and its slots of the sorted records: the records in that
+// order, then records without a window up to a whole number of groups, so that
+// no group mixes two polynomials.
+__global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__restrict__ plans,
+                                                           const long long *__restrict__ pstart,
+                                                           const int32_t *__restrict__ gstart,
+                                                           const double2 *__restrict__ z, double2 *__restrict__ m_out,
+                                                           long long *__restrict__ e_out, int32_t *__restrict__ terms,
+                                                           EvalWs W) {
+    __shared__ double s_k[kHullLds];
+    __shared__ double s_s[kHullLds];
+    __shared__ int32_t s_key[kBatchMaxPoints];
+    const int t = threadIdx.x;
+    const int pidx = blockIdx.x;
+    if (pidx == 0 && t < 64) W.ctl[t] = 0;            // totals and counters of the later kernels
+    const DevPlan P = plans[pidx];
+    const long long p0 = pstart[pidx];
+    const int m = (int)(pstart[pidx + 1] - p0);
+    const int g0 = gstart[pidx], ng = gstart[pidx + 1] - g0;
+    const bool in_lds = P.nh <= kHullLds;
+    if (in_lds)
+        for (int i = t; i < P.nh; i += kBatchThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+    __syncthreads();
+    const double *hk = in_lds ? s_k : P.hull_k;
+    const double *hs = in_lds ? s_s : P.hull_s;
+    int np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (int j = t; j < np2; j += kBatchThreads) {
+        int key = INT_MAX;
+        if (j < m)
+            key = bounds_point(P, hk, hs, z, (int)(p0 + j), m_out, e_out, nullptr, nullptr, terms, nullptr, W) *
+                      kBatchMaxPoints + j;
+        s_key[j] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int h = k >> 1; h > 0; h >>= 1) {
+            for (int i = t; i < np2; i += kBatchThreads) {
+                const int o = i ^ h;
+                if (o > i) {
+                    const int a = s_key[i], b = s_key[o];
+                    if ((a > b) == ((i & k) == 0)) { s_key[i] = b; s_key[o] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = t; q < ng * kWave; q += kBatchThreads) {
+        const size_t dst = (size_t)g0 * kWave + q;
+        if (q < m) {
+            const int j = s_key[q] % kBatchMaxPoints;
+            W.srec[dst] = W.rec[p0 + j];
+            W.sperm[dst] = (int)(p0 + j);
+        } else {
+            PointRec rc;
+            rc.z = make_double2(0.0, 0.0);
+            rc.l = 1;
+            rc.r = 0;
+            rc.eref = 0;
+            W.srec[dst] = rc;
+            W.sperm[dst] = -1;
+        }
+    }
+}
+
 // One wavefront per group of 64 sorted points: the union window, the largest
 // window start and the tile cost; then, per workgroup of kGroupsPerBlock
 // groups, the exclusive prefix of the costs (gcum) and their total (gblk_sum).
@@ -410,8 +485,9 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
         const int nvalid = valid_points(W);
         const int idx = g * kWave + lane;
         int l = INT_MAX, r = INT_MIN;
-        if (idx < nvalid) { const PointRec &rc = W.srec[idx]; l = rc.l; r = rc.r; }
-        const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(idx < nvalid ? l : INT_MIN);
+        // records without a window (a batch's padding and finished points) do not count
+        if (idx < nvalid) { const PointRec &rc = W.srec[idx]; if (rc.l <= rc.r) { l = rc.l; r = rc.r; } }
+        const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(l != INT_MAX ? l : INT_MIN);
         cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, P.chunk, W.cost_shift)) : 0;
         if (lane == 0) {
             W.glo[g] = lo;
@@ -795,7 +871,30 @@ __device__ __forceinline__ long long deriv_eref(long long eref, int ez, int r) {
 // fixed-point form of a partial value (qr + i qi) 2^E relative to 2^eref: a
 // high word (integer part of value 2^(fix_shift - eref)) and a low word
 // (fix_lo more bits), summed exactly across chunks
-__device__ __forceinline__ void fix_add(const DevPlan &P, double qr, double qi, long long E, long long eref,
+// The fields of a polynomial's plan that the tile kernels read per group: of the
+// kernel's plan, or in a batch of the group's own plan (scalar loads).
+struct SegPlan {
+    const_table_t cf;
+    const_table32_t c32;
+    const FPE_CONST_AS int32_t *sig32;
+    int coef_shift, fix_shift, fix_lo;
+};
+typedef const FPE_CONST_AS DevPlan *const_plans_t;
+
+template <bool B>
+__device__ __forceinline__ SegPlan group_plan(const DevPlan &P, const EvalWs &W, int g) {
+    if constexpr (B) {
+        const int gp = __builtin_amdgcn_readfirstlane(W.gpoly[g]);
+        const_plans_t pl = (const_plans_t)W.plans;
+        return {(const_table_t)pl[gp].coef, (const_table32_t)pl[gp].coef32,
+                (const FPE_CONST_AS int32_t *)pl[gp].sig32, pl[gp].coef_shift, pl[gp].fix_shift, pl[gp].fix_lo};
+    } else {
+        return {(const_table_t)P.coef, (const_table32_t)P.coef32, (const FPE_CONST_AS int32_t *)P.sig32,
+                P.coef_shift, P.fix_shift, P.fix_lo};
+    }
+}
+
+__device__ __forceinline__ void fix_add(const SegPlan &P, double qr, double qi, long long E, long long eref,
                                         long long &a0, long long &a1, long long &a2, long long &a3) {
     long long sh = E - eref + P.fix_shift;
     sh = sh < -2200 ? -2200 : (sh > 200 ? 200 : sh);
@@ -807,17 +906,17 @@ __device__ __forceinline__ void fix_add(const DevPlan &P, double qr, double qi, 
     a3 += (long long)rint(ldexp(xi - hi0, P.fix_lo));
 }
 
-__device__ __forceinline__ void fix_out(const DevPlan &P, long long a0, long long a1, long long a2, long long a3,
+__device__ __forceinline__ void fix_out(int fix_shift, int fix_lo, long long a0, long long a1, long long a2, long long a3,
                                         long long eref, double2 &m, long long &e) {
-    const int f = P.fix_shift;
-    const double vr = ldexp((double)a0, -f) + ldexp((double)a1, -f - P.fix_lo);
-    const double vi = ldexp((double)a2, -f) + ldexp((double)a3, -f - P.fix_lo);
+    const int f = fix_shift;
+    const double vr = ldexp((double)a0, -f) + ldexp((double)a1, -f - fix_lo);
+    const double vi = ldexp((double)a2, -f) + ldexp((double)a3, -f - fix_lo);
     normalise(vr, vi, eref, m, e);
 }
 
 // With D, the same pass also sums the derivative of the kept terms,
 // Q'(z) = sum k a_k z^(k-1) over G_p within [l, r], into (md_out, ed_out).
-template <bool D>
+template <bool D, bool B>
 __global__ __launch_bounds__(kWindowThreads) __attribute__((amdgpu_waves_per_eu(D ? 5 : 6)))
 void k_window(DevPlan P, double2 *__restrict__ m_out,
                                                            long long *__restrict__ e_out,
@@ -835,9 +934,6 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
     const int C = P.chunk;
-    // the coefficient table is read-only for the whole evaluation: wave-uniform
-    // indices into it become scalar loads
-    const_table_t cf = (const_table_t)P.coef;
     int g, c, ge, ce;
     {
         const int2 st = W.wstart[w], en = W.wstart[w + 1];
@@ -862,6 +958,10 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         const int glo = __builtin_amdgcn_readfirstlane(W.glo[g]);
         const int ghi = __builtin_amdgcn_readfirstlane(W.ghi[g]);
         const int clo = glo / C, chi = ghi / C;
+        // the coefficient tables are read-only for the whole evaluation:
+        // wave-uniform indices into them become scalar loads
+        const SegPlan S = group_plan<B>(P, W, g);
+        const_table_t cf = S.cf;
         const int seg_c0 = c;
         const int idx = g * kWave + lane;
         const bool valid = idx < nvalid;
@@ -880,7 +980,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         const bool z32ok = !valid || (ez >= -11 && ez <= 12);
         const float zr32 = (float)ldexp(wr, ez), zi32 = (float)ldexp(wi, ez);
         double z8r = 0.0, z8i = 0.0;
-        if (!D && P.coef32) {
+        if (!D && S.c32) {
             FPE_NO_CONTRACT
             double ar = ldexp(wr, ez), ai = ldexp(wi, ez);
             for (int q = 0; q < 3; ++q) {
@@ -913,11 +1013,11 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 // active lane's |z| allow it, then the ragged bottom in FP64
                 bool f32 = false;
                 if constexpr (!D) {
-                    if (P.coef32 && Ahi >= Alo) {
-                        const int sg = __builtin_amdgcn_readfirstlane(P.sig32[c]);
+                    if (S.c32 && Ahi >= Alo) {
+                        const int sg = __builtin_amdgcn_readfirstlane(S.sig32[c]);
                         f32 = sg != kNoFp32 && __ballot(act && !z32ok) == 0;
                         if (f32) {
-                            run_f32(acc.hr, acc.hi, zr32, zi32, z8r, z8i, (const_table32_t)P.coef32, sg, Khi, Alo,
+                            run_f32(acc.hr, acc.hi, zr32, zi32, z8r, z8i, S.c32, sg, Khi, Alo,
                                     Ahi, hi);
                             run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
                         }
@@ -934,7 +1034,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 }
                 if (act) {
                     // times z^lo = (pr + i pi) 2^(pe + lo ez)
-                    const long long E = P.coef_shift + pe + (long long)lo * ez;
+                    const long long E = S.coef_shift + pe + (long long)lo * ez;
                     const double qr = fma(acc.hr, pr, -acc.hi * pi);
                     const double qi = fma(acc.hr, pi, acc.hi * pr);
                     double dqr = 0.0, dqi = 0.0;
@@ -962,9 +1062,9 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                         }
                     } else {
                         const long long eref = W.srec[idx].eref;
-                        fix_add(P, qr, qi, E, eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
+                        fix_add(S, qr, qi, E, eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
                         if constexpr (D)
-                            fix_add(P, dqr, dqi, E - ez, deriv_eref(eref, ez, r), s_acc[4][t], s_acc[5][t],
+                            fix_add(S, dqr, dqi, E - ez, deriv_eref(eref, ez, r), s_acc[4][t], s_acc[5][t],
                                     s_acc[6][t], s_acc[7][t]);
                     }
                 }
@@ -982,12 +1082,12 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 double2 m;
                 long long e;
                 const long long eref = W.srec[idx].eref;
-                fix_out(P, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t], eref, m, e);
+                fix_out(S.fix_shift, S.fix_lo, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t], eref, m, e);
                 const int j = W.sperm[idx];
                 m_out[j] = m;
                 e_out[j] = e;
                 if constexpr (D) {
-                    fix_out(P, s_acc[4][t], s_acc[5][t], s_acc[6][t], s_acc[7][t], deriv_eref(eref, ez, r), m, e);
+                    fix_out(S.fix_shift, S.fix_lo, s_acc[4][t], s_acc[5][t], s_acc[6][t], s_acc[7][t], deriv_eref(eref, ez, r), m, e);
                     md_out[j] = m;
                     ed_out[j] = e;
                 }
@@ -1012,7 +1112,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 constexpr int kFinalThreads = 1024;
 constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
 
-template <bool D>
+template <bool D, bool B>
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out,
                                                             double2 *__restrict__ md_out,
@@ -1051,13 +1151,19 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
                 if (rc.l / P.chunk != rc.r / P.chunk) {
                     double2 m;
                     long long e;
-                    fix_out(P, a[0], a[1], a[2], a[3], rc.eref, m, e);
+                    int fs = P.fix_shift, fl = P.fix_lo;
+                    if constexpr (B) {
+                        const DevPlan &Q = W.plans[W.gpoly[g]];
+                        fs = Q.fix_shift;
+                        fl = Q.fix_lo;
+                    }
+                    fix_out(fs, fl, a[0], a[1], a[2], a[3], rc.eref, m, e);
                     const int j = W.sperm[p];
                     m_out[j] = m;
                     e_out[j] = e;
                     if constexpr (D) {
                         const int ez = exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y)));
-                        fix_out(P, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
+                        fix_out(fs, fl, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
                         md_out[j] = m;
                         ed_out[j] = e;
                     }
@@ -1211,8 +1317,8 @@ __global__ __launch_bounds__(256) void k_grad_z(DevPlan P, const double2 *__rest
 int g_num_cu = 0;
 // the kernels that run the (group, chunk) tiles: values, values and
 // derivatives, adjoint
-enum TileKernel { kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2 };
-int g_window_blocks_per_cu[3] = {0, 0, 0};
+enum TileKernel { kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2, kTileBatch = 3 };
+int g_window_blocks_per_cu[4] = {0, 0, 0, 0};
 
 // wavefronts of a tile kernel: as many as are resident at once on the device
 // (the partition hands each one an equal share, so none may wait for a second
@@ -1238,15 +1344,17 @@ hipError_t prof_event(hipEvent_t *ev) {
 // compute units and resident window workgroups per compute unit (once per process)
 hipError_t device_setup() {
     if (g_num_cu > 0) return hipSuccess;
-    int dev = 0, ncu = 0, nb[3] = {0, 0, 0};
+    int dev = 0, ncu = 0, nb[4] = {0, 0, 0, 0};
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const void *kern[3] = {reinterpret_cast<const void *>(k_window<false>),
-                           reinterpret_cast<const void *>(k_window<true>), reinterpret_cast<const void *>(k_adjoint)};
-    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+    const void *kern[4] = {reinterpret_cast<const void *>(k_window<false, false>),
+                           reinterpret_cast<const void *>(k_window<true, false>),
+                           reinterpret_cast<const void *>(k_adjoint),
+                           reinterpret_cast<const void *>(k_window<false, true>)};
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb[i], kern[i], kWindowThreads, 0);
     if (e != hipSuccess) return e;
-    for (int i = 0; i < 3; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
+    for (int i = 0; i < 4; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
     g_num_cu = ncu > 0 ? ncu : 256;
     return hipSuccess;
 }
@@ -1276,25 +1384,34 @@ __global__ __launch_bounds__(256) void k_newton(const double2 *__restrict__ z, i
 // Smallest cost unit shift for which the total tile work of n points fits the
 // int32 scans: at most G groups x (chunks x (C / u + powering overhead) + the
 // per-group part), u = 16 << shift; -1 if none does.
+int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk);
+
 int cost_shift_for(const DevPlan &P, int64_t n) {
     const int64_t G = (n + kWave - 1) / kWave;
     const int64_t chunks = P.nh > 0 ? (int64_t)P.dt / P.chunk - (int64_t)P.v / P.chunk + 1 : 0;
+    return cost_shift_for_chunks(G, chunks, P.chunk);
+}
+
+int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
     for (int sh = 0; sh <= 20; ++sh) {
         const int64_t u = (int64_t)kCostUnit << sh;
         auto units = [u](int64_t steps) { return (steps + u - 1) / u; };
-        const int64_t per_tile = units(P.chunk + kTileSteps + kGroupSteps + kPowSteps * 31 * 2);
+        const int64_t per_tile = units(chunk + kTileSteps + kGroupSteps + kPowSteps * 31 * 2);
         const int64_t bound = G * chunks * per_tile;
         if (bound < INT32_MAX) return sh;
     }
     return -1;
 }
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind) {
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind, int64_t batch_groups) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
-    const int64_t G = (n + kWave - 1) / kWave;
-    const int64_t NB = (n + kSortPoints - 1) / kSortPoints;
+    // a batch sorts each polynomial's points in its own whole groups (no sort table)
+    const bool batch = batch_groups >= 0;
+    const int64_t G = batch ? batch_groups : (n + kWave - 1) / kWave;
+    const int64_t nslot = batch ? G * kWave : n;
+    const int64_t NB = batch ? 0 : (n + kSortPoints - 1) / kSortPoints;
     const int64_t tlen = (int64_t)(kBins + 1) * NB;
     const int tab_ib = NB <= kSeg ? (int)(kSeg / (NB > 0 ? NB : 1)) : 1;
     const int64_t nblk_g = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
@@ -1302,8 +1419,8 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     EvalWs w;
     w.rec = (PointRec *)take(sizeof(PointRec) * n);
     w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
-    w.srec = (PointRec *)take(sizeof(PointRec) * n);
-    w.sperm = (int32_t *)take(sizeof(int32_t) * n);
+    w.srec = (PointRec *)take(sizeof(PointRec) * nslot);
+    w.sperm = (int32_t *)take(sizeof(int32_t) * nslot);
     w.table = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.tscan = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.bin_sum = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));
@@ -1321,7 +1438,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     // one workspace serves every tile kernel
     const int64_t nw_max = std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
-                                    window_waves(kTileAdjoint));
+                                    std::max(window_waves(kTileAdjoint), window_waves(kTileBatch)));
     w.n_waves = window_waves(kind);
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
@@ -1331,6 +1448,9 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.cost_shift = cost_shift_for(P, n);
     w.n_groups = G;
     w.n_sort_blocks = NB;
+    w.plans = nullptr;
+    w.gpoly = nullptr;
+    w.n_slots = batch ? nslot : -1;
     if (ws) *ws = w;
     return off;
 }
@@ -1350,6 +1470,17 @@ extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t
 }
 
 // The kernels before the tile kernel: bounds, sort, groups, partition.
+// From the sorted records: group windows and costs, their scan, the partition.
+static void launch_groups(const DevPlan &P, const EvalWs &W, int nblk_g, hipStream_t stream) {
+    k_groups<<<(unsigned)nblk_g, 1024, 0, stream>>>(P, W);
+    if (nblk_g > kPartLds) {
+        const int nseg = (nblk_g + kSeg - 1) / kSeg;
+        k_scan_seg<<<(unsigned)nseg, 1024, 0, stream>>>(W.gblk_sum, W.gblk_pre, nblk_g, W.gseg_sum);
+        k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg, W.gseg_off, W.ctl + 0);
+    }
+    k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 1023) / 1024), 1024, 0, stream>>>(P, W);
+}
+
 static hipError_t launch_front(const DevPlan &P, const double2 *z, int ni, double2 *m, long long *e, double2 *md,
                                long long *ed, int32_t *terms, long long *win, const EvalWs &W, hipStream_t stream) {
     const unsigned sb = (unsigned)W.n_sort_blocks;
@@ -1360,13 +1491,7 @@ static hipError_t launch_front(const DevPlan &P, const double2 *z, int ni, doubl
         const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
         k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
         k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
-        k_groups<<<(unsigned)nblk_g, 1024, 0, stream>>>(P, W);
-        if (nblk_g > kPartLds) {
-            const int nseg = (nblk_g + kSeg - 1) / kSeg;
-            k_scan_seg<<<(unsigned)nseg, 1024, 0, stream>>>(W.gblk_sum, W.gblk_pre, nblk_g, W.gseg_sum);
-            k_scan_sums<<<1, 1024, 0, stream>>>(W.gseg_sum, nseg, W.gseg_off, W.ctl + 0);
-        }
-        k_partition<<<(unsigned)((W.n_groups + W.n_waves + 1 + 1023) / 1024), 1024, 0, stream>>>(P, W);
+        launch_groups(P, W, nblk_g, stream);
     }
     return hipGetLastError();
 }
@@ -1408,16 +1533,16 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
             FPE_HIP_CHECK(prof_event(&ev1));
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
-        if (deriv) k_window<true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, md, ed, W);
-        else k_window<false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        if (deriv) k_window<true, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, md, ed, W);
+        else k_window<false, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         if (g_prof.on) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
         if (W.n_waves > 1) {
             const unsigned fb = (unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks);
-            if (deriv) k_finalize<true><<<fb, kFinalThreads, 0, stream>>>(P, m, e, md, ed, W);
-            else k_finalize<false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+            if (deriv) k_finalize<true, false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, md, ed, W);
+            else k_finalize<false, false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         }
     }
     FPE_HIP_CHECK(hipGetLastError());
@@ -1519,6 +1644,177 @@ extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int
             k_grad_z<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
                 P, z, ni, g, reinterpret_cast<const double2 *>(md_dev), reinterpret_cast<const long long *>(ed_dev),
                 reinterpret_cast<double2 *>(grad_z_dev), ga);
+    }
+    FPE_HIP_CHECK(hipGetLastError());
+    set_error("");
+    return FPE_OK;
+}
+
+// ---------------------------------------------------------------- batches
+struct fpe_batch_s {
+    int32_t n_poly;
+    int64_t n_points, n_groups;
+    DevPlan rep;                   // the first plan (every plan has the same chunk length)
+    const DevPlan *plans_dev;      // per polynomial, in the batch workspace
+    const long long *pstart_dev;   // n_poly + 1 point offsets
+    const int32_t *gstart_dev;     // n_poly + 1 group offsets
+    const int32_t *gpoly_dev;      // per group: its polynomial
+    int32_t cost_shift;
+    int device;
+};
+
+namespace {
+
+struct BatchLayout { size_t plans, pstart, gstart, gpoly, total; };
+
+BatchLayout batch_layout(int64_t n_poly, int64_t n_groups) {
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.plans = take(sizeof(DevPlan) * (size_t)n_poly);
+    L.pstart = take(sizeof(long long) * (size_t)(n_poly + 1));
+    L.gstart = take(sizeof(int32_t) * (size_t)(n_poly + 1));
+    L.gpoly = take(sizeof(int32_t) * (size_t)(n_groups > 0 ? n_groups : 1));
+    L.total = off;
+    return L;
+}
+
+// checks the point offsets and counts the groups
+fpe_status batch_groups(int32_t n_poly, const int64_t *z_offsets, int64_t *n_groups) {
+    if (n_poly < 1) return fail(FPE_ERR_INVALID_ARG, "n_poly must be >= 1");
+    if (!z_offsets) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (z_offsets[0] != 0) return fail(FPE_ERR_INVALID_ARG, "z_offsets[0] must be 0");
+    int64_t g = 0;
+    for (int32_t i = 0; i < n_poly; ++i) {
+        const int64_t m = z_offsets[i + 1] - z_offsets[i];
+        if (m < 0) return fail(FPE_ERR_INVALID_ARG, "z_offsets must be non-decreasing");
+        if (m > kBatchMaxPoints)
+            return fail(FPE_ERR_UNSUPPORTED, "a polynomial of a batch has more than " +
+                                                 std::to_string(kBatchMaxPoints) + " points (use fpe_eval)");
+        g += (m + kWave - 1) / kWave;
+    }
+    if (z_offsets[n_poly] >= INT32_MAX || g * kWave >= INT32_MAX)
+        return fail(FPE_ERR_INVALID_ARG, "too many points");
+    *n_groups = g;
+    return FPE_OK;
+}
+
+}  // namespace
+
+extern "C" fpe_status fpe_batch_workspace_size(int32_t n_poly, const int64_t *z_offsets, size_t *bytes) {
+    if (!bytes) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    int64_t g = 0;
+    fpe_status st = batch_groups(n_poly, z_offsets, &g);
+    if (st != FPE_OK) return st;
+    *bytes = batch_layout(n_poly, g).total;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, const int64_t *z_offsets,
+                                       void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                                       fpe_batch_t *out_batch) {
+    if (!plans || !out_batch || !workspace_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    *out_batch = nullptr;
+    int64_t G = 0;
+    fpe_status st = batch_groups(n_poly, z_offsets, &G);
+    if (st != FPE_OK) return st;
+    const BatchLayout L = batch_layout(n_poly, G);
+    if (workspace_bytes < L.total)
+        return fail(FPE_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(L.total));
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0)
+        return fail(FPE_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    std::vector<DevPlan> hp(n_poly);
+    std::vector<long long> ps(n_poly + 1);
+    std::vector<int32_t> gs(n_poly + 1), gp((size_t)(G > 0 ? G : 1), 0);
+    int64_t chunks_max = 1;
+    gs[0] = 0;
+    for (int32_t i = 0; i < n_poly; ++i) {
+        if (!plans[i]) return fail(FPE_ERR_INVALID_ARG, "NULL plan in the batch");
+        if (plans[i]->device != plans[0]->device) return fail(FPE_ERR_INVALID_ARG, "plans on different devices");
+        hp[i] = plans[i]->dev;
+        const DevPlan &Q = hp[i];
+        if (Q.nh > 0) chunks_max = std::max<int64_t>(chunks_max, (int64_t)Q.dt / Q.chunk - (int64_t)Q.v / Q.chunk + 1);
+        ps[i] = z_offsets[i];
+        const int32_t ng = (int32_t)((z_offsets[i + 1] - z_offsets[i] + kWave - 1) / kWave);
+        gs[i + 1] = gs[i] + ng;
+        for (int32_t k = gs[i]; k < gs[i + 1]; ++k) gp[k] = i;
+    }
+    ps[n_poly] = z_offsets[n_poly];
+    const int cs = cost_shift_for_chunks(G, chunks_max, kChunk);
+    if (cs < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    char *b = static_cast<char *>(workspace_dev);
+    FPE_HIP_CHECK(hipMemcpyAsync(b + L.plans, hp.data(), sizeof(DevPlan) * hp.size(), hipMemcpyHostToDevice, stream));
+    FPE_HIP_CHECK(hipMemcpyAsync(b + L.pstart, ps.data(), sizeof(long long) * ps.size(), hipMemcpyHostToDevice, stream));
+    FPE_HIP_CHECK(hipMemcpyAsync(b + L.gstart, gs.data(), sizeof(int32_t) * gs.size(), hipMemcpyHostToDevice, stream));
+    FPE_HIP_CHECK(hipMemcpyAsync(b + L.gpoly, gp.data(), sizeof(int32_t) * gp.size(), hipMemcpyHostToDevice, stream));
+    FPE_HIP_CHECK(hipStreamSynchronize(stream));
+    std::unique_ptr<fpe_batch_s> bt(new fpe_batch_s());
+    bt->n_poly = n_poly;
+    bt->n_points = z_offsets[n_poly];
+    bt->n_groups = G;
+    bt->rep = hp[0];
+    bt->plans_dev = reinterpret_cast<const DevPlan *>(b + L.plans);
+    bt->pstart_dev = reinterpret_cast<const long long *>(b + L.pstart);
+    bt->gstart_dev = reinterpret_cast<const int32_t *>(b + L.gstart);
+    bt->gpoly_dev = reinterpret_cast<const int32_t *>(b + L.gpoly);
+    bt->cost_shift = cs;
+    bt->device = plans[0]->device;
+    *out_batch = bt.release();
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_batch_destroy(fpe_batch_t batch) {
+    delete batch;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_eval_batched_workspace_size(fpe_batch_t batch, size_t *bytes) {
+    if (!batch || !bytes) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    FPE_HIP_CHECK(device_setup());       // the resident wavefronts size the partition's tables
+    *bytes = eval_workspace_bytes(batch->rep, batch->n_points, nullptr, nullptr, kTileBatch, batch->n_groups);
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, double *m_dev, int64_t *e_dev,
+                                       int32_t *terms_dev, void *workspace_dev, size_t workspace_bytes,
+                                       hipStream_t stream) {
+    if (!batch) return fail(FPE_ERR_INVALID_ARG, "NULL batch");
+    const int64_t n = batch->n_points;
+    if (n == 0) { set_error(""); return FPE_OK; }
+    if (!z_dev || !m_dev || !e_dev || !workspace_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    FPE_HIP_CHECK(device_setup());
+    size_t need = 0;
+    fpe_status st = fpe_eval_batched_workspace_size(batch, &need);
+    if (st != FPE_OK) return st;
+    if (workspace_bytes < need)
+        return fail(FPE_ERR_WORKSPACE, "eval workspace too small: need " + std::to_string(need));
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0 || reinterpret_cast<uintptr_t>(z_dev) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(m_dev) % 16 != 0)
+        return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
+    EvalWs W;
+    eval_workspace_bytes(batch->rep, n, &W, workspace_dev, kTileBatch, batch->n_groups);
+    W.plans = batch->plans_dev;
+    W.gpoly = batch->gpoly_dev;
+    W.cost_shift = batch->cost_shift;
+    const DevPlan &P = batch->rep;
+    const double2 *z = reinterpret_cast<const double2 *>(z_dev);
+    double2 *m = reinterpret_cast<double2 *>(m_dev);
+    long long *e = reinterpret_cast<long long *>(e_dev);
+    k_bbounds<<<(unsigned)batch->n_poly, kBatchThreads, 0, stream>>>(batch->plans_dev, batch->pstart_dev,
+                                                                      batch->gstart_dev, z, m, e, terms_dev, W);
+    if (W.n_groups > 0) {
+        const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
+        launch_groups(P, W, nblk_g, stream);
+        const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
+        k_window<false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        if (W.n_waves > 1) {
+            const unsigned fb = (unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks);
+            k_finalize<false, true><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        }
     }
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");

@@ -71,9 +71,16 @@ struct EvalWs {
     int64_t n, n_groups, n_sort_blocks, n_waves;
     int32_t cost_shift;           // tile work is counted in units of (16 << cost_shift) steps
     int32_t tab_ib;               // bins per table-scan segment
+    // a batch of polynomials (else NULL / -1): the plan of each group, and the
+    // number of sorted slots (every polynomial's points padded to whole groups
+    // with records that have no window)
+    const DevPlan *plans;
+    const int32_t *gpoly;
+    int64_t n_slots;
 };
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind);
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind,
+                            int64_t batch_groups = -1);
 
 // Read-only tables are read through the constant address space in device code:
 // a wave-uniform index then becomes a scalar load, one per wavefront, broadcast
