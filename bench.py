@@ -157,6 +157,66 @@ def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> 
     return out
 
 
+def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
+    """4096 polynomials, degrees log-uniform in [16, 65536], 64..1024 spherical
+    points each (FP64, p = 53): preconditioning of every plan (timed apart),
+    the batch's chunk length from the autotuner, then fpe_eval_batched over all
+    points, eagerly and as a replayed HIP graph, beside one fpe_eval per
+    polynomial in a loop."""
+    coeffs, points = workloads.batched_workload()
+    t0 = time.perf_counter()
+    plans = [fpe.precondition(torch.from_numpy(c).to(dev), 53) for c in coeffs]
+    torch.cuda.synchronize()
+    pre_ms = (time.perf_counter() - t0) * 1e3
+    offs = np.concatenate([[0], np.cumsum([len(z) for z in points])])
+    batch = fpe.Batch(plans, offs)
+    z = torch.from_numpy(np.concatenate(points)).to(dev)
+    n = z.shape[0]
+    chunk = batch.autotune(z)
+    out = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+    batch.eval(z, out=out)
+    torch.cuda.synchronize()
+
+    def timed(fn, k):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    eager_ms = timed(lambda: batch.eval(z, out=out), steps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.eval(z, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.eval(z, out=out)
+    graph_ms = timed(g.replay, steps)
+    zs = [z[offs[i]:offs[i + 1]] for i in range(len(plans))]
+    loop_ms = timed(lambda: [p.eval(zz) for p, zz in zip(plans, zs)], 1)
+    mm, ee = out[0].cpu().numpy(), out[1].cpu().numpy()
+    rng = np.random.default_rng(12347)
+    worst = 0.0
+    for i in rng.choice(len(coeffs), 16, replace=False):
+        ref = oracle.precondition(coeffs[i], 53).eval(points[i])
+        sl = slice(offs[i], offs[i + 1])
+        worst = max(worst, float(oracle.scaled_error(mm[sl], ee[sl], ref["m"], ref["e"], ref["dwin_m"],
+                                                     ref["dwin_e"]).max()))
+    log(f"batch of {len(plans)} polynomials, {n} points: eager {eager_ms:.3f} ms, graph replay {graph_ms:.3f} ms, "
+        f"per-polynomial loop {loop_ms:.1f} ms (chunk {chunk}); preconditioning {pre_ms:.0f} ms; "
+        f"max scaled error (16 polynomials) {worst:.2e}")
+    return {"workload": "batched_4096", "n_poly": len(plans), "n_points": n,
+            "coefficients": int(sum(len(c) for c in coeffs)), "unit": "evaluations/s", "chunk": chunk,
+            "eager": {"ms": eager_ms, "value": n / (eager_ms * 1e-3)},
+            "graph_replay": {"ms": graph_ms, "value": n / (graph_ms * 1e-3)},
+            "per_polynomial_loop": {"ms": loop_ms, "value": n / (loop_ms * 1e-3)},
+            "precondition_ms": pre_ms, "max_scaled_err_16_polys": worst}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +228,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f3", action="store_true", help="skip the derivative / adjoint / Newton leg")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 (p = 24) leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-polynomial leg")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="chunk length of the tiles (0: autotuned before the timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--check-sample", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -201,6 +264,14 @@ def main() -> int:
     info = plan.info()
     log(f"precondition {pre_ms:.1f} ms: {info}")
 
+    # the tile schedule: the autotuner's chunk length (or a given one), chosen
+    # before the timed region like the preconditioning
+    if args.chunk:
+        plan.set_chunk(args.chunk)
+        chunk = args.chunk
+    else:
+        chunk = plan.autotune(z)
+    log(f"chunk length {chunk}")
     # one untimed pass for the algorithmic work counts
     m, e, terms, window = plan.eval(z, terms=True, window=True)
     torch.cuda.synchronize()
@@ -257,7 +328,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "d": d, "n_points": n, "p_bits": wl.p_bits,
                    "coefficients": "Re, Im i.i.d. uniform[-1,1]", "points": "uniform on the Riemann sphere",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "chunk": chunk},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "k_window", "kernel_ms": win_avg_ms,
@@ -298,6 +369,8 @@ def main() -> int:
         res["adjoint_newton"] = adjoint_leg(fpe, workloads, torch, dev, args.steps)
     if not args.no_fp32:
         res["fp32_p24"] = fp32_leg(fpe, workloads, oracle, np, torch, dev, args.steps, args.check_sample)
+    if not args.no_batched:
+        res["batched"] = batched_leg(fpe, workloads, oracle, np, torch, dev, args.steps)
 
     if not args.no_cpu:
         threads = oracle.default_threads()

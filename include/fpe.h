@@ -283,6 +283,35 @@ fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, double *m_de
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Tile schedule: the chunk length C of the (point group, chunk) tiles        */
+/* (the paper's window sum, Section 5.2, is cut into pieces of C coefficients */
+/* that are summed exactly; C changes the work split, not the method).        */
+/* ------------------------------------------------------------------------- */
+
+/* Sets the chunk length of later evaluations of this plan: a power of two in
+ * [256, 2048], or 0 for the automatic choice (the length fpe_autotune found for
+ * the same bucket of degree and point count earlier in this process, else 512).
+ * FP32 plans accept only 0 and 512 (FPE_ERR_UNSUPPORTED otherwise).  Errors:
+ * FPE_ERR_INVALID_ARG. */
+fpe_status fpe_plan_set_chunk(fpe_plan_t plan, int32_t chunk);
+
+/* Times fpe_eval of these n points (writing m, e as fpe_eval does) with each
+ * candidate chunk length 256, 512, 1024, 2048 (one untimed and three timed
+ * calls each, HIP events on stream; the call waits), keeps the fastest for this
+ * plan, records it for the plan's bucket (bit length of d, bit length of n) in a
+ * process-wide cache that untuned plans consult, and writes it to *chunk_out
+ * (may be NULL).  FP32 plans keep 512.  Arguments and errors as fpe_eval. */
+fpe_status fpe_autotune(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
+                        void *workspace_dev, size_t workspace_bytes, hipStream_t stream, int32_t *chunk_out);
+
+/* The same for a batch (fpe_eval_batched; the cache bucket is the mean degree
+ * and the point count of the batch). */
+fpe_status fpe_batch_set_chunk(fpe_batch_t batch, int32_t chunk);
+fpe_status fpe_batch_autotune(fpe_batch_t batch, const double *z_dev, double *m_dev, int64_t *e_dev,
+                              void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                              int32_t *chunk_out);
+
+/* ------------------------------------------------------------------------- */
 /* Same-GPU baseline: Horner's rule on the full polynomial (Section 1).      */
 /* ------------------------------------------------------------------------- */
 

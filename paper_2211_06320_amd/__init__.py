@@ -91,6 +91,14 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_batched_workspace_size.argtypes = [vp, P(sz)]
     L.fpe_eval_batched.restype = i32
     L.fpe_eval_batched.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_plan_set_chunk.restype = i32
+    L.fpe_plan_set_chunk.argtypes = [vp, i32]
+    L.fpe_autotune.restype = i32
+    L.fpe_autotune.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp, P(i32)]
+    L.fpe_batch_set_chunk.restype = i32
+    L.fpe_batch_set_chunk.argtypes = [vp, i32]
+    L.fpe_batch_autotune.restype = i32
+    L.fpe_batch_autotune.argtypes = [vp, vp, vp, vp, vp, sz, vp, P(i32)]
     L.fpe_eval_adjoint.restype = i32
     L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_horner_eval.restype = i32
@@ -232,6 +240,23 @@ class Plan:
         return m, e
 
 
+    def set_chunk(self, chunk: int) -> None:
+        """Chunk length of the tiles for later evaluations (0: automatic)."""
+        _check(lib().fpe_plan_set_chunk(self._h, int(chunk)))
+
+    def autotune(self, z, stream=None) -> int:
+        """Times the candidate chunk lengths on these points, keeps the fastest."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        n = z.shape[0]
+        m = torch.empty(n, dtype=torch.complex128, device=z.device)
+        e = torch.empty(n, dtype=torch.int64, device=z.device)
+        ws, nb = self.workspace(n)
+        c = ctypes.c_int32()
+        _check(lib().fpe_autotune(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), ws, nb, _stream(stream),
+                                  ctypes.byref(c)))
+        return c.value
+
     def eval_deriv(self, z, stream=None):
         """Q_lambda(z) and its derivative through the same window; returns
         (m, e, md, ed) with Q = m 2^e and Q' = md 2^ed."""
@@ -325,6 +350,22 @@ class Batch:
         if h is not None and h.value and destroy is not None:
             destroy(h)
             self._h = None
+
+    def set_chunk(self, chunk: int) -> None:
+        """Chunk length of the tiles for later evaluations (0: automatic)."""
+        _check(lib().fpe_batch_set_chunk(self._h, int(chunk)))
+
+    def autotune(self, z, stream=None) -> int:
+        """Times the candidate chunk lengths on these points, keeps the fastest."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        n = self.n_points
+        m = torch.empty(n, dtype=torch.complex128, device=z.device)
+        e = torch.empty(n, dtype=torch.int64, device=z.device)
+        c = ctypes.c_int32()
+        _check(lib().fpe_batch_autotune(self._h, z.data_ptr(), m.data_ptr(), e.data_ptr(), self._eval_ws,
+                                        self._eval_nb, _stream(stream), ctypes.byref(c)))
+        return c.value
 
     def eval(self, z, terms: bool = False, out=None, stream=None):
         """Q_lambda at every point of every polynomial: (m, e) or (m, e, terms)."""

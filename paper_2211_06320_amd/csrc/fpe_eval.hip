@@ -39,7 +39,10 @@
 // coefficient per step for all of its lanes.
 #include <algorithm>
 #include <climits>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -488,7 +491,7 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
         // records without a window (a batch's padding and finished points) do not count
         if (idx < nvalid) { const PointRec &rc = W.srec[idx]; if (rc.l <= rc.r) { l = rc.l; r = rc.r; } }
         const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(l != INT_MAX ? l : INT_MIN);
-        cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, P.chunk, W.cost_shift)) : 0;
+        cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, W.chunk, W.cost_shift)) : 0;
         if (lane == 0) {
             W.glo[g] = lo;
             W.ghi[g] = hi;
@@ -570,7 +573,7 @@ __device__ __forceinline__ int2 wave_start(const GroupCost &gc, int g, long long
 // (G, 0) past the end of the work and for the sentinel w = NW
 __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     __shared__ int32_t s_off[kPartLds];
-    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = P.chunk;
+    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = W.chunk;
     const int nblk = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
     BlockOffsets bo{nullptr, W.gblk_pre, W.gseg_off};
     long long total;
@@ -933,7 +936,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
     if (w >= W.n_waves) return;
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
-    const int C = P.chunk;
+    const int C = W.chunk;
     int g, c, ge, ce;
     {
         const int2 st = W.wstart[w], en = W.wstart[w + 1];
@@ -1013,7 +1016,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 // active lane's |z| allow it, then the ragged bottom in FP64
                 bool f32 = false;
                 if constexpr (!D) {
-                    if (S.c32 && Ahi >= Alo) {
+                    if (S.c32 && C == kChunk && Ahi >= Alo) {
                         const int sg = __builtin_amdgcn_readfirstlane(S.sig32[c]);
                         f32 = sg != kNoFp32 && __ballot(act && !z32ok) == 0;
                         if (f32) {
@@ -1125,7 +1128,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
         const int g = W.split[it];
         const int2 gw = W.gwave[g];
         int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
-        resolve_tile(W, P.chunk, fg, fc);
+        resolve_tile(W, W.chunk, fg, fc);
         const int side0 = fg == g ? 0 : 1;
         long long a[kAccWords] = {};
         for (int w = gw.x + q; w <= gw.y; w += nq) {
@@ -1148,7 +1151,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
             const int p = g * kWave + lane;
             if (p < valid_points(W)) {
                 const PointRec rc = W.srec[p];
-                if (rc.l / P.chunk != rc.r / P.chunk) {
+                if (rc.l / W.chunk != rc.r / W.chunk) {
                     double2 m;
                     long long e;
                     int fs = P.fix_shift, fl = P.fix_lo;
@@ -1200,7 +1203,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
     if (w >= W.n_waves) return;
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
-    const int C = P.chunk;
+    const int C = W.chunk;
     int g, c, ge, ce;
     {
         const int2 st = W.wstart[w], en = W.wstart[w + 1];
@@ -1386,10 +1389,10 @@ __global__ __launch_bounds__(256) void k_newton(const double2 *__restrict__ z, i
 // per-group part), u = 16 << shift; -1 if none does.
 int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk);
 
-int cost_shift_for(const DevPlan &P, int64_t n) {
+int cost_shift_for(const DevPlan &P, int64_t n, int C) {
     const int64_t G = (n + kWave - 1) / kWave;
-    const int64_t chunks = P.nh > 0 ? (int64_t)P.dt / P.chunk - (int64_t)P.v / P.chunk + 1 : 0;
-    return cost_shift_for_chunks(G, chunks, P.chunk);
+    const int64_t chunks = P.nh > 0 ? (int64_t)P.dt / C - (int64_t)P.v / C + 1 : 0;
+    return cost_shift_for_chunks(G, chunks, C);
 }
 
 int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
@@ -1403,7 +1406,8 @@ int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
     return -1;
 }
 
-size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind, int64_t batch_groups) {
+size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind, int64_t batch_groups,
+                            int chunk) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
@@ -1445,7 +1449,8 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
     w.tab_ib = tab_ib;
-    w.cost_shift = cost_shift_for(P, n);
+    w.cost_shift = cost_shift_for(P, n, chunk);
+    w.chunk = chunk;
     w.n_groups = G;
     w.n_sort_blocks = NB;
     w.plans = nullptr;
@@ -1459,10 +1464,45 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
 
 using namespace fpe;
 
+// ---------------------------------------------------------------- tile schedule
+// The chunk length C of the (group, chunk) tiles: the one fpe_autotune chose or
+// fpe_plan_set_chunk set for this plan, else the one tuned earlier in this
+// process for the same (degree, points, FP32, batch) bucket, else kChunk.  FP32
+// plans keep kChunk (their FP32 table is scaled per kChunk coefficients).
+namespace {
+std::map<std::tuple<int, int, int, int>, int> g_tuned_chunk;
+std::mutex g_tuned_mu;
+
+int bucket(int64_t x) {
+    int b = 0;
+    while (x > 0) { ++b; x >>= 1; }
+    return b;
+}
+
+std::tuple<int, int, int, int> tune_key(int64_t d, int64_t n, bool fp32, bool batch) {
+    return {bucket(d), bucket(n), fp32 ? 1 : 0, batch ? 1 : 0};
+}
+
+int cached_chunk(const std::tuple<int, int, int, int> &key) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned_chunk.find(key);
+    return it == g_tuned_chunk.end() ? kChunk : it->second;
+}
+
+bool valid_chunk(int c) { return c >= kChunkMin && c <= kChunkMax && (c & (c - 1)) == 0; }
+
+int plan_chunk(const fpe_plan_s *plan, int64_t n) {
+    if (plan->dev.coef32) return kChunk;
+    if (plan->chunk_sel) return plan->chunk_sel;
+    return cached_chunk(tune_key(plan->d, n, false, false));
+}
+}  // namespace
+
 extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t *bytes) {
     if (!plan || !bytes) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
-    if (cost_shift_for(plan->dev, n) < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    if (cost_shift_for(plan->dev, n, kChunkMin) < 0)
+        return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
     FPE_HIP_CHECK(device_setup());
     *bytes = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, kTileValue);
     set_error("");
@@ -1513,7 +1553,7 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
         reinterpret_cast<uintptr_t>(m_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue);
+    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue, -1, plan_chunk(plan, n));
     const DevPlan &P = plan->dev;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
     double2 *m = reinterpret_cast<double2 *>(m_dev);
@@ -1630,7 +1670,7 @@ extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int
     if (ga) k_zero2<<<(unsigned)((na + 255) / 256), 256, 0, stream>>>(ga, na);
     if (n > 0) {
         EvalWs W;
-        eval_workspace_bytes(P, n, &W, workspace_dev, kTileAdjoint);
+        eval_workspace_bytes(P, n, &W, workspace_dev, kTileAdjoint, -1, plan_chunk(plan, n));
         const double2 *z = reinterpret_cast<const double2 *>(z_dev);
         const double2 *g = reinterpret_cast<const double2 *>(g_dev);
         const int ni = (int)n;
@@ -1661,9 +1701,19 @@ struct fpe_batch_s {
     const int32_t *gpoly_dev;      // per group: its polynomial
     int32_t cost_shift;
     int device;
+    int64_t max_span;              // the longest trimmed coefficient range of its plans
+    int64_t mean_degree;
+    bool any_fp32;
+    int32_t chunk_sel = 0;         // chosen by fpe_batch_autotune or set; 0: cached choice or default
 };
 
 namespace {
+
+int batch_chunk(const fpe_batch_s *b) {
+    if (b->any_fp32) return kChunk;
+    if (b->chunk_sel) return b->chunk_sel;
+    return cached_chunk(tune_key(b->mean_degree, b->n_points, false, true));
+}
 
 struct BatchLayout { size_t plans, pstart, gstart, gpoly, total; };
 
@@ -1727,21 +1777,27 @@ extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, 
     std::vector<DevPlan> hp(n_poly);
     std::vector<long long> ps(n_poly + 1);
     std::vector<int32_t> gs(n_poly + 1), gp((size_t)(G > 0 ? G : 1), 0);
-    int64_t chunks_max = 1;
+    int64_t chunks_max = 1, span_max = 1, deg_sum = 0;
+    bool any_fp32 = false;
     gs[0] = 0;
     for (int32_t i = 0; i < n_poly; ++i) {
         if (!plans[i]) return fail(FPE_ERR_INVALID_ARG, "NULL plan in the batch");
         if (plans[i]->device != plans[0]->device) return fail(FPE_ERR_INVALID_ARG, "plans on different devices");
         hp[i] = plans[i]->dev;
         const DevPlan &Q = hp[i];
-        if (Q.nh > 0) chunks_max = std::max<int64_t>(chunks_max, (int64_t)Q.dt / Q.chunk - (int64_t)Q.v / Q.chunk + 1);
+        if (Q.nh > 0) {
+            chunks_max = std::max<int64_t>(chunks_max, (int64_t)Q.dt / kChunkMin - (int64_t)Q.v / kChunkMin + 1);
+            span_max = std::max<int64_t>(span_max, (int64_t)Q.dt - Q.v + 1);
+        }
+        deg_sum += plans[i]->d;
+        any_fp32 = any_fp32 || Q.coef32 != nullptr;
         ps[i] = z_offsets[i];
         const int32_t ng = (int32_t)((z_offsets[i + 1] - z_offsets[i] + kWave - 1) / kWave);
         gs[i + 1] = gs[i] + ng;
         for (int32_t k = gs[i]; k < gs[i + 1]; ++k) gp[k] = i;
     }
     ps[n_poly] = z_offsets[n_poly];
-    const int cs = cost_shift_for_chunks(G, chunks_max, kChunk);
+    const int cs = cost_shift_for_chunks(G, chunks_max, kChunkMin);
     if (cs < 0) return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
     char *b = static_cast<char *>(workspace_dev);
     FPE_HIP_CHECK(hipMemcpyAsync(b + L.plans, hp.data(), sizeof(DevPlan) * hp.size(), hipMemcpyHostToDevice, stream));
@@ -1760,6 +1816,9 @@ extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, 
     bt->gpoly_dev = reinterpret_cast<const int32_t *>(b + L.gpoly);
     bt->cost_shift = cs;
     bt->device = plans[0]->device;
+    bt->max_span = span_max;
+    bt->mean_degree = deg_sum / n_poly;
+    bt->any_fp32 = any_fp32;
     *out_batch = bt.release();
     set_error("");
     return FPE_OK;
@@ -1796,10 +1855,11 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
         reinterpret_cast<uintptr_t>(m_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(batch->rep, n, &W, workspace_dev, kTileBatch, batch->n_groups);
+    const int C = batch_chunk(batch);
+    eval_workspace_bytes(batch->rep, n, &W, workspace_dev, kTileBatch, batch->n_groups, C);
     W.plans = batch->plans_dev;
     W.gpoly = batch->gpoly_dev;
-    W.cost_shift = batch->cost_shift;
+    W.cost_shift = cost_shift_for_chunks(batch->n_groups, batch->max_span / C + 2, C);
     const DevPlan &P = batch->rep;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
     double2 *m = reinterpret_cast<double2 *>(m_dev);
@@ -1817,6 +1877,104 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
         }
     }
     FPE_HIP_CHECK(hipGetLastError());
+    set_error("");
+    return FPE_OK;
+}
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+
+const int kChunkCandidates[] = {256, 512, 1024, 2048};
+
+// average time of three calls of f on the stream, after one untimed call
+template <class F>
+fpe_status time_calls(F &&f, hipStream_t stream, float *ms) {
+    fpe_status st = f();
+    if (st != FPE_OK) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    FPE_HIP_CHECK(hipEventCreate(&a));
+    FPE_HIP_CHECK(hipEventCreate(&b));
+    FPE_HIP_CHECK(hipEventRecord(a, stream));
+    for (int r = 0; r < 3 && st == FPE_OK; ++r) st = f();
+    FPE_HIP_CHECK(hipEventRecord(b, stream));
+    FPE_HIP_CHECK(hipEventSynchronize(b));
+    float t = 0.0f;
+    FPE_HIP_CHECK(hipEventElapsedTime(&t, a, b));
+    FPE_HIP_CHECK(hipEventDestroy(a));
+    FPE_HIP_CHECK(hipEventDestroy(b));
+    *ms = t / 3.0f;
+    return st;
+}
+
+}  // namespace
+
+extern "C" fpe_status fpe_plan_set_chunk(fpe_plan_t plan, int32_t chunk) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (chunk != 0 && !valid_chunk(chunk)) return fail(FPE_ERR_INVALID_ARG, "chunk must be 0 or a power of two in [256, 2048]");
+    if (chunk != 0 && chunk != kChunk && plan->dev.coef32)
+        return fail(FPE_ERR_UNSUPPORTED, "FP32 plans use the chunk length 512");
+    plan->chunk_sel = chunk;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_autotune(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
+                                   void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                                   int32_t *chunk_out) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    const bool fp32 = plan->dev.coef32 != nullptr;
+    int best = kChunk;
+    float best_ms = -1.0f;
+    if (!fp32 && n > 0) {
+        for (int C : kChunkCandidates) {
+            plan->chunk_sel = C;
+            float ms = 0.0f;
+            fpe_status st = time_calls([&] {
+                return fpe_eval(plan, z_dev, n, m_dev, e_dev, nullptr, nullptr, workspace_dev, workspace_bytes, stream);
+            }, stream, &ms);
+            if (st != FPE_OK) { plan->chunk_sel = 0; return st; }
+            if (best_ms < 0.0f || ms < best_ms) { best_ms = ms; best = C; }
+        }
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned_chunk[tune_key(plan->d, n, false, false)] = best;
+    }
+    plan->chunk_sel = fp32 ? 0 : best;
+    if (chunk_out) *chunk_out = best;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_batch_set_chunk(fpe_batch_t batch, int32_t chunk) {
+    if (!batch) return fail(FPE_ERR_INVALID_ARG, "NULL batch");
+    if (chunk != 0 && !valid_chunk(chunk)) return fail(FPE_ERR_INVALID_ARG, "chunk must be 0 or a power of two in [256, 2048]");
+    if (chunk != 0 && chunk != kChunk && batch->any_fp32)
+        return fail(FPE_ERR_UNSUPPORTED, "batches with FP32 plans use the chunk length 512");
+    batch->chunk_sel = chunk;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_batch_autotune(fpe_batch_t batch, const double *z_dev, double *m_dev, int64_t *e_dev,
+                                         void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                                         int32_t *chunk_out) {
+    if (!batch) return fail(FPE_ERR_INVALID_ARG, "NULL batch");
+    int best = kChunk;
+    float best_ms = -1.0f;
+    if (!batch->any_fp32 && batch->n_points > 0) {
+        for (int C : kChunkCandidates) {
+            batch->chunk_sel = C;
+            float ms = 0.0f;
+            fpe_status st = time_calls([&] {
+                return fpe_eval_batched(batch, z_dev, m_dev, e_dev, nullptr, workspace_dev, workspace_bytes, stream);
+            }, stream, &ms);
+            if (st != FPE_OK) { batch->chunk_sel = 0; return st; }
+            if (best_ms < 0.0f || ms < best_ms) { best_ms = ms; best = C; }
+        }
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned_chunk[tune_key(batch->mean_degree, batch->n_points, false, true)] = best;
+    }
+    batch->chunk_sel = batch->any_fp32 ? 0 : best;
+    if (chunk_out) *chunk_out = best;
     set_error("");
     return FPE_OK;
 }

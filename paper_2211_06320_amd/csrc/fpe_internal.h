@@ -16,7 +16,9 @@ namespace fpe {
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kHullLds = 512;             // cover vertices staged in LDS by the plan kernel
 constexpr double kEta = 0x1p-20;          // widening of the window ends before ceil/floor
-constexpr int kChunk = 512;               // coefficient chunk length C of the window kernel
+constexpr int kChunk = 512;               // default coefficient chunk length C of the window kernel
+constexpr int kChunkMin = 256;            // shortest chunk an evaluation may use (sizes the fixed point)
+constexpr int kChunkMax = 2048;
 constexpr int32_t kNegInfScale = INT32_MIN;
 
 // Device view of a preconditioned polynomial.  All pointers point into the
@@ -77,10 +79,11 @@ struct EvalWs {
     const DevPlan *plans;
     const int32_t *gpoly;
     int64_t n_slots;
+    int32_t chunk;                // coefficient chunk length C of the tiles (a power of two)
 };
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind,
-                            int64_t batch_groups = -1);
+                            int64_t batch_groups = -1, int chunk = kChunk);
 
 // Read-only tables are read through the constant address space in device code:
 // a wave-uniform index then becomes a scalar load, one per wavefront, broadcast
@@ -242,6 +245,7 @@ struct fpe_plan_s {
     std::vector<int64_t> hull_k, hull_s;
     std::vector<uint8_t> good;       // d + 1 entries
     int device;
+    int32_t chunk_sel = 0;           // chunk length chosen by fpe_autotune or set; 0: cached choice or default
 };
 
 namespace fpe {

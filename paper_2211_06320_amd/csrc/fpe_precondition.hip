@@ -314,7 +314,8 @@ extern "C" fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_
     // W / 4 < 2^(bitlen(W) - 2); the low word holds fix_lo more bits of each
     // partial and its sum over at most `chunks` partials stays below 2^62
     const int64_t wmax = std::max<int64_t>(plan->dt - plan->v + 1, 1);
-    const int64_t chunks = std::max<int64_t>(plan->dt / P.chunk - plan->v / P.chunk + 1, 1);
+    // (counted for the shortest chunk an evaluation may choose)
+    const int64_t chunks = std::max<int64_t>(plan->dt / kChunkMin - plan->v / kChunkMin + 1, 1);
     P.fix_shift = (int32_t)(60 - bitlen(wmax));
     P.fix_lo = (int32_t)std::min<int64_t>(44, 62 - bitlen(chunks));
     P.coef_shift = (int32_t)shift;
