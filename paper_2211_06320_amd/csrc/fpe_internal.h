@@ -243,7 +243,7 @@ struct fpe_plan_s {
     fpe::DevPlan dev;
     int64_t d, v, dt, nh, ngood, T, p, smax, smin_good;
     std::vector<int64_t> hull_k, hull_s;
-    std::vector<uint8_t> good;       // d + 1 entries
+    const int32_t *good_dev = nullptr;   // d + 1 flags of G_p, in the plan's workspace
     int device;
     int32_t chunk_sel = 0;           // chunk length chosen by fpe_autotune or set; 0: cached choice or default
 };

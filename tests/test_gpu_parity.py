@@ -105,6 +105,13 @@ def _plan_cases():
         "monomial": np.array([0, 0, 0, 2 - 1j], complex),
         "constant": np.array([3 + 4j], complex),
         "all_zero": np.zeros(7, complex),
+        # every scale value in [-1000, 1000] at many indices: the most cover candidates
+        "many_scales_d20000": np.exp2(np.random.default_rng(11).integers(-1000, 1001, 20001).astype(float))
+                              * np.exp(1j * np.random.default_rng(12).uniform(0, 2 * np.pi, 20001)),
+        # s(a_k) = k + 1 exactly: every point on one line, two vertices
+        "collinear_d100": np.exp2(n.astype(float)).astype(complex),
+        # a level profile with a single raised point
+        "level_d300": np.concatenate([np.ones(150), [2.0 ** 40], np.ones(150)]).astype(complex),
     }
     return cases
 
@@ -117,6 +124,22 @@ def test_plan_bit_exact(fpe, name, p):
     plan = fpe.precondition(to_dev(c), p)
     torch.cuda.synchronize()
     assert_plan_matches(plan, c, p)
+
+
+def test_plan_extreme_scales(fpe):
+    """Subnormal and near-overflow coefficients: the scales span the whole FP64
+    range; either the plan matches the oracle, or (good coefficients too far
+    apart for FP64 window sums) it is refused with FPE_ERR_UNSUPPORTED."""
+    c = np.array([5e-324, 1e-300, 1.0, 1e300, 1.7e308, 1e-310j, 3 + 4j], complex)
+    for p in (53, 6):
+        try:
+            plan = fpe.precondition(to_dev(c), p)
+        except fpe.FPEError as err:
+            assert err.status == 6
+            continue
+        assert_plan_matches(plan, c, p)
+    with pytest.raises(fpe.FPEError):
+        fpe.precondition(to_dev(np.array([1.0, np.nan, 2.0], complex)), 53)
 
 
 # ----------------------------------------------------------------------------- evaluation
