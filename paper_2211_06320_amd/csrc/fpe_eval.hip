@@ -1112,7 +1112,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 // (integer sums: the order does not matter).  The first owner
 // may hold the group as its last segment (slot 1); every later owner holds it
 // as its first segment (slot 0).
-constexpr int kFinalThreads = 1024;
+constexpr int kFinalThreads = 512;
 constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
 
 template <bool D, bool B>
@@ -1177,12 +1177,6 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
     }
 }
 
-// sum over the 64 lanes (every lane gets it)
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
 // Adjoint of the window sums with respect to the coefficients: for upstream
 // gradients gin_j (per point, input order), grad_a[k] += sum over the points j
 // whose kept terms include k (k in G_p within [l_j, r_j]) of gin_j conj(z_j)^k
@@ -1191,9 +1185,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Same tiles and partition as k_window: each lane starts from gin conj(z^lo)
 // (z^lo by tile_power) and multiplies by conj(z) per step, mantissa and
 // exponent apart, so that a term is rounded to the double range only when it
-// is emitted; the 64 lanes' terms of each k are summed across the wavefront
-// and added to grad_a[k] (FP64 atomics: the order of the additions, hence the
-// last bits, can vary).
+// is emitted; the 64 lanes' terms of four consecutive k at a time are summed
+// across the wavefront by a reduce-scatter and added to grad_a[k] (FP64
+// atomics: the order of the additions, hence the last bits, can vary).
 __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const double2 *__restrict__ gin,
                                                             double2 *__restrict__ grad_a, EvalWs W) {
     const int lane = threadIdx.x % kWave;
@@ -1253,27 +1247,50 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                 double tr = fma(gr, pr, gi * pi);
                 double ti = fma(gi, pr, -gr * pi);
                 long long E = (long long)eg + pe + (long long)lo * ez;
-                for (int k = Klo; k <= Khi; ++k) {
-                    const bool on = act && k >= lo && k <= hi;
-                    double vr = 0.0, vi = 0.0;
-                    if (on) {
-                        const int sh = (int)(E < -2200 ? -2200 : (E > 2200 ? 2200 : E));
-                        vr = ldexp(tr, sh);
-                        vi = ldexp(ti, sh);
-                        const double nr = fma(tr, wr, ti * wi);       // times conj(w)
-                        ti = fma(ti, wr, -tr * wi);
-                        tr = nr;
-                        E += ez;
+                // four indices at a time: each lane's four terms, then a
+                // reduce-scatter over the wavefront (xor 32 and 16 leave lanes
+                // 16 q .. 16 q + 15 with index q; xor 8, 4, 2, 1 sum those)
+                const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+                for (int k0 = Klo; k0 <= Khi; k0 += 4) {
+                    double vr[4], vi[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = k0 + j;
+                        vr[j] = 0.0;
+                        vi[j] = 0.0;
+                        if (act && k >= lo && k <= hi) {
+                            const int sh = (int)(E < -2200 ? -2200 : (E > 2200 ? 2200 : E));
+                            vr[j] = ldexp(tr, sh);
+                            vi[j] = ldexp(ti, sh);
+                            const double nr = fma(tr, wr, ti * wi);       // times conj(w)
+                            ti = fma(ti, wr, -tr * wi);
+                            tr = nr;
+                            E += ez;
+                        }
                     }
-                    // only terms of G_p: their coefficients are the nonzero entries
-                    // of the masked table
-                    const double2 a = P.coef[k];
-                    if (a.x != 0.0 || a.y != 0.0) {
-                        vr = wave_sum(vr);
-                        vi = wave_sum(vi);
-                        if (lane == 0 && (vr != 0.0 || vi != 0.0)) {
-                            atomicAdd(&grad_a[k].x, vr);
-                            atomicAdd(&grad_a[k].y, vi);
+                    // xor 32: keep indices {0, 1} (b5 clear) or {2, 3}, add the partner's
+                    double ar = b5 ? vr[2] : vr[0], ai = b5 ? vi[2] : vi[0];
+                    double br = b5 ? vr[3] : vr[1], bi = b5 ? vi[3] : vi[1];
+                    ar += __shfl_xor(b5 ? vr[0] : vr[2], 32, kWave);
+                    ai += __shfl_xor(b5 ? vi[0] : vi[2], 32, kWave);
+                    br += __shfl_xor(b5 ? vr[1] : vr[3], 32, kWave);
+                    bi += __shfl_xor(b5 ? vi[1] : vi[3], 32, kWave);
+                    // xor 16: keep the first (b4 clear) or the second of the pair
+                    double xr = b4 ? br : ar, xi = b4 ? bi : ai;
+                    xr += __shfl_xor(b4 ? ar : br, 16, kWave);
+                    xi += __shfl_xor(b4 ? ai : bi, 16, kWave);
+                    for (int o = 8; o > 0; o >>= 1) {
+                        xr += __shfl_xor(xr, o, kWave);
+                        xi += __shfl_xor(xi, o, kWave);
+                    }
+                    const int k = k0 + ((lane >> 4) & 3);
+                    // only terms of G_p: their coefficients are the nonzero
+                    // entries of the masked table
+                    if ((lane & 15) == 0 && k <= Khi && (xr != 0.0 || xi != 0.0)) {
+                        const double2 a = P.coef[k];
+                        if (a.x != 0.0 || a.y != 0.0) {
+                            atomicAdd(&grad_a[k].x, xr);
+                            atomicAdd(&grad_a[k].y, xi);
                         }
                     }
                 }
