@@ -64,9 +64,10 @@ def window_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str):
+def recorded_traffic(workload: str, chunk: int):
     """HBM bytes per window-kernel launch from the committed counter summary, or
-    None when it is missing, for another workload, or for other kernel sources."""
+    None when it is missing, for another workload or chunk length, or for other
+    kernel sources."""
     if workload != "uniform_d1e6" or not os.path.exists(TRAFFIC_PROFILE):
         return None
     kv = {}
@@ -78,7 +79,7 @@ def recorded_traffic(workload: str):
     if kv.get("window_sources_sha256") != window_sources_sha256():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch_c{chunk}"])
     except (KeyError, ValueError):
         return None
 
@@ -309,7 +310,7 @@ def main() -> int:
     value = n / (ms_per_step * 1e-3)
     win_avg_ms = win_ms / max(launches, 1)
     achieved = flops / (win_avg_ms * 1e-3) / 1e12
-    traffic = recorded_traffic(wl.name)
+    traffic = recorded_traffic(wl.name, chunk)
     log(f"eval {ms_per_step:.3f} ms/step ({value:.3e} evals/s); window kernel {win_avg_ms:.3f} ms, "
         f"{achieved:.2f} TFLOP/s algorithmic")
 

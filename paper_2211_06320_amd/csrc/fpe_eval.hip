@@ -1112,7 +1112,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 // (integer sums: the order does not matter).  The first owner
 // may hold the group as its last segment (slot 1); every later owner holds it
 // as its first segment (slot 0).
-constexpr int kFinalThreads = 512;
+constexpr int kFinalThreads = 1024;
 constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
 
 template <bool D, bool B>
@@ -1145,6 +1145,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
         for (int k = 0; k < kAccWords; ++k) part[q][lane][k] = a[k];
         __syncthreads();
         if (q == 0) {
+#pragma nounroll
             for (int qq = 1; qq < nq; ++qq)
 #pragma unroll
                 for (int k = 0; k < kAccWords; ++k) a[k] += part[qq][lane][k];
@@ -1460,7 +1461,9 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     // one workspace serves every tile kernel
     const int64_t nw_max = std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
                                     std::max(window_waves(kTileAdjoint), window_waves(kTileBatch)));
-    w.n_waves = window_waves(kind);
+    // as many window wavefronts as are resident, but no more than four per
+    // group: a small evaluation then spreads its few tiles over few wavefronts
+    w.n_waves = std::min<int64_t>(window_waves(kind), std::max<int64_t>(4 * G, 1));
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
