@@ -571,6 +571,19 @@ __device__ __forceinline__ int2 wave_start(const GroupCost &gc, int g, long long
 // [G, G + NW]: per wavefront, its first tile as (group, chunk), or (group, -1)
 // for "the first tile of the first group with tiles at or after this one";
 // (G, 0) past the end of the work and for the sentinel w = NW
+// fixed-point words per lane and window-wavefront slot: the sums of Q, then of Q'
+constexpr int kSlotWords = 8;
+
+// Split groups whose windows span more than kFinalShort + 1 window wavefronts
+// are long groups: the finalize kernel cuts their owners into pieces of
+// kLongPiece and spreads the pieces over its grid.  Owner ranges of two groups
+// share at most one wavefront, so an evaluation over n_waves wavefronts has
+// fewer than long_cap(n_waves) long groups.
+constexpr int kFinalShort = 8;
+constexpr int kLongPiece = 16;
+constexpr int kLongLds = 2048;        // long groups the finalize kernel holds in LDS
+__host__ __device__ inline int long_cap(int64_t n_waves) { return (int)(n_waves / kFinalShort + 1); }
+
 __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     __shared__ int32_t s_off[kPartLds];
     const int G = (int)W.n_groups, NW = (int)W.n_waves, C = W.chunk;
@@ -591,13 +604,23 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
         total = W.ctl[0];
     }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    {
+        // the finalize kernel's accumulators of long groups start at zero
+        const int64_t nacc = (int64_t)long_cap(NW) * kWave * kSlotWords / 2;
+        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+        longlong2 *acc = reinterpret_cast<longlong2 *>(W.lacc);
+        for (int64_t k = i; k < nacc; k += nthr) acc[k] = make_longlong2(0, 0);
+        if (i < long_cap(NW)) W.lcnt[i] = 0;
+    }
     if (i < G) {
         const int g = (int)i;
         const int cost = W.gcost[g];
         if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
         const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
         const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
-        W.gwave[g] = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
+        const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
+        W.gwave[g] = gw;
+        if (gw.y - gw.x >= kFinalShort) W.lgroups[atomicAdd(W.ctl + 9, 1)] = g;
         return;
     }
     if (i > (int64_t)G + NW) return;
@@ -621,8 +644,11 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     const int2 st = wave_start(gc, g, A, B, sw);
     W.wstart[w] = st;
     // w starts inside g and g's first tile belongs to w - 1: g is split, and
-    // w is its second owner (this identifies each split group once)
-    if (st.x == g && div_floor(A * NW, total) == w - 1) W.split[atomicAdd(W.ctl + 8, 1)] = g;
+    // w is its second owner (this identifies each split group once); long
+    // groups have their own list
+    if (st.x == g && div_floor(A * NW, total) == w - 1 &&
+        div_floor((B - gc.last) * NW, total) - (w - 1) < kFinalShort)
+        W.split[atomicAdd(W.ctl + 8, 1)] = g;
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -861,9 +887,6 @@ __device__ __forceinline__ void tile_power(PowState &ps, int l, int lo, bool act
     }
 }
 
-// fixed-point words per lane and window-wavefront slot: the sums of Q, then of Q'
-constexpr int kSlotWords = 8;
-
 // reference exponent of the derivative's terms k a_k z^(k-1): each is below
 // r 2^(N - lambda), and with lambda >= ez - 1 (z = w 2^ez) and eref = floor(N) + 2,
 // eref + 1 - ez + bitlen(r) bounds floor(N - lambda) + 2 + bitlen(r) from above
@@ -954,7 +977,6 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * kSlotWords;
         for (int k = 0; k < kAccWords; ++k) s0[k] = 0;
     }
-    bool first_segment = true;
     // one pass per group segment: the consecutive tiles of one group this
     // wavefront owns
     while (g < G && !(g == ge && c == ce)) {
@@ -1076,9 +1098,12 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
             if (c == chi || (g == ge && c + 1 == ce)) break;
             ++c;
         }
-        // ---- end of the segment: a group done entirely here is written out, a
-        // part of a group leaves its fixed-point sums in this wavefront's slot
-        // (0: its first segment, 1: its last)
+        // ---- end of the segment: a group done entirely here is written out; a
+        // part of a group leaves its fixed-point sums in this wavefront's slot 0
+        // if earlier wavefronts own the group's first tiles, and in slot 1 if
+        // later ones own its last tiles (a middle owner writes both; only the
+        // first segment can start inside a group, only the last can end inside
+        // one, so no slot is written twice)
         if (multi) {
             const int t = threadIdx.x;
             if (seg_c0 == clo && c == chi) {
@@ -1095,11 +1120,13 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                     ed_out[j] = e;
                 }
             } else {
-                long long *slot = W.slots + ((size_t)(2 * w + (first_segment ? 0 : 1)) * kWave + lane) * kSlotWords;
-                for (int k = 0; k < kAccWords; ++k) slot[k] = s_acc[k][t];
+                long long *slot = W.slots + ((size_t)(2 * w) * kWave + lane) * kSlotWords;
+                if (seg_c0 != clo)
+                    for (int k = 0; k < kAccWords; ++k) slot[k] = s_acc[k][t];
+                if (c != chi)
+                    for (int k = 0; k < kAccWords; ++k) slot[kWave * kSlotWords + k] = s_acc[k][t];
             }
         }
-        first_segment = false;
         if (c < chi) { ++c; }
         else { ++g; c = -1; resolve_tile(W, C, g, c); }
     }
@@ -1107,13 +1134,72 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 
 // Points whose window spans several chunks, in groups split across
 // wavefronts: the sum of the fixed-point partials the owning wavefronts left
-// in their slots.  k_partition lists the split groups; workgroups take list
-// entries in turn and stride their threads over the owning wavefronts
-// (integer sums: the order does not matter).  The first owner
-// may hold the group as its last segment (slot 1); every later owner holds it
-// as its first segment (slot 0).
+// in their slots (integer sums: the order does not matter).  The first owner
+// holds the group in its slot 1, every later owner in its slot 0.  Work items
+// of the grid's wavefronts: the short split groups k_partition listed (one
+// wavefront sums all owners), then the pieces of the long groups (a wavefront
+// sums kLongPiece owners and adds them to the group's accumulator with
+// device-scope atomics; the piece that arrives last writes the outputs).  A
+// long group's slots, up to one per window wavefront, are so read by many
+// compute units at once.
 constexpr int kFinalThreads = 1024;
-constexpr int kFinalBlocks = 1024;   // workgroups walking the list of split groups
+constexpr int kFinalBlocks = 1024;    // workgroups of the finalize grid, at most
+static_assert(kLongLds == 2 * kFinalThreads, "the piece scan takes two long groups per thread");
+
+// the outputs of one point of a split group from its summed partials
+template <bool D, bool B>
+__device__ __forceinline__ void final_out(const DevPlan &P, const EvalWs &W, int g, const PointRec &rc,
+                                          int j, const long long *a, double2 *__restrict__ m_out,
+                                          long long *__restrict__ e_out, double2 *__restrict__ md_out,
+                                          long long *__restrict__ ed_out) {
+    double2 m;
+    long long e;
+    int fs = P.fix_shift, fl = P.fix_lo;
+    if constexpr (B) {
+        const DevPlan &Q = W.plans[W.gpoly[g]];
+        fs = Q.fix_shift;
+        fl = Q.fix_lo;
+    }
+    fix_out(fs, fl, a[0], a[1], a[2], a[3], rc.eref, m, e);
+    m_out[j] = m;
+    e_out[j] = e;
+    if constexpr (D) {
+        const int ez = exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y)));
+        fix_out(fs, fl, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
+        md_out[j] = m;
+        ed_out[j] = e;
+    }
+}
+
+// adds the slots of owners w0 .. min(w0 + 3, wy) of a group whose first owner
+// is wx to a; the loads are all issued before the first sum
+template <int kAccWords>
+__device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w0, int lane, long long *a) {
+    constexpr int kU = 4;
+    longlong2 x[kU][kAccWords / 2];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int w = w0 + u;                             // the same for the whole wavefront
+        if (w <= wy) {
+            const longlong2 *sl = reinterpret_cast<const longlong2 *>(
+                W.slots + ((size_t)(2 * w + (w == wx ? 1 : 0)) * kWave + lane) * kSlotWords);
+#pragma unroll
+            for (int k = 0; k < kAccWords / 2; ++k) x[u][k] = sl[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kAccWords / 2; ++k) x[u][k] = make_longlong2(0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+        for (int k = 0; k < kAccWords / 2; ++k) {
+            a[2 * k] += x[u][k].x;
+            a[2 * k + 1] += x[u][k].y;
+        }
+}
+
+__device__ __forceinline__ int long_pieces(int2 gw) { return (gw.y - gw.x + kLongPiece) / kLongPiece; }
 
 template <bool D, bool B>
 __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
@@ -1121,60 +1207,99 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
                                                             double2 *__restrict__ md_out,
                                                             long long *__restrict__ ed_out, EvalWs W) {
     constexpr int kAccWords = D ? 8 : 4;
-    __shared__ long long part[kFinalThreads / kWave][kWave][kAccWords];
-    const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave, nq = kFinalThreads / kWave;
-    const int nsplit = W.ctl[8];
-    for (int it = blockIdx.x; it < nsplit; it += gridDim.x) {
-        const int g = W.split[it];
-        const int2 gw = W.gwave[g];
-        int fg = W.wstart[gw.x].x, fc = W.wstart[gw.x].y;
-        resolve_tile(W, W.chunk, fg, fc);
-        const int side0 = fg == g ? 0 : 1;
-        long long a[kAccWords] = {};
-        for (int w = gw.x + q; w <= gw.y; w += nq) {
-            const longlong2 *sl = reinterpret_cast<const longlong2 *>(
-                W.slots + ((size_t)(2 * w + (w == gw.x ? side0 : 0)) * kWave + lane) * kSlotWords);
-#pragma unroll
-            for (int k = 0; k < kAccWords / 2; ++k) {
-                const longlong2 x = sl[k];
-                a[2 * k] += x.x;
-                a[2 * k + 1] += x.y;
-            }
+    constexpr int nq = kFinalThreads / kWave;
+    __shared__ int s_lg[kLongLds];            // the long groups,
+    __shared__ int2 s_lgw[kLongLds];          //   their owner ranges
+    __shared__ int s_pre[kLongLds];           //   and the inclusive prefix of their pieces
+    __shared__ int s_wsum[nq];
+    const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave;
+    const int nsplit = W.ctl[8], nlong = W.ctl[9];
+    const int nvalid = valid_points(W);
+    int npieces = 0;
+    if (nlong > 0) {                                   // the same for every thread
+        for (int i = threadIdx.x; i < nlong; i += kFinalThreads) {
+            const int g = W.lgroups[i];
+            s_lg[i] = g;
+            s_lgw[i] = W.gwave[g];
         }
-#pragma unroll
-        for (int k = 0; k < kAccWords; ++k) part[q][lane][k] = a[k];
         __syncthreads();
-        if (q == 0) {
-#pragma nounroll
-            for (int qq = 1; qq < nq; ++qq)
+        const int i0 = 2 * threadIdx.x;
+        const int c0 = i0 < nlong ? long_pieces(s_lgw[i0]) : 0;
+        const int c1 = i0 + 1 < nlong ? long_pieces(s_lgw[i0 + 1]) : 0;
+        int incl = c0 + c1;
 #pragma unroll
-                for (int k = 0; k < kAccWords; ++k) a[k] += part[qq][lane][k];
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int t = __shfl_up(incl, d);
+            if (lane >= d) incl += t;
+        }
+        if (lane == kWave - 1) s_wsum[q] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int r = 0; r < nq; ++r) {
+            const int ws = s_wsum[r];
+            if (r < q) before += ws;
+            npieces += ws;
+        }
+        const int excl = before + incl - c0 - c1;
+        if (i0 < nlong) s_pre[i0] = excl + c0;
+        if (i0 + 1 < nlong) s_pre[i0 + 1] = excl + c0 + c1;
+        __syncthreads();
+    }
+    // work items in wavefront order q * gridDim.x + blockIdx.x: neighbouring
+    // items go to different workgroups
+    const int nwork = nsplit + npieces;
+    for (int u = q * (int)gridDim.x + (int)blockIdx.x; u < nwork; u += (int)gridDim.x * nq) {
+        if (u < nsplit) {
+            const int g = W.split[u];
+            const int2 gw = W.gwave[g];
             const int p = g * kWave + lane;
-            if (p < valid_points(W)) {
-                const PointRec rc = W.srec[p];
-                if (rc.l / W.chunk != rc.r / W.chunk) {
-                    double2 m;
-                    long long e;
-                    int fs = P.fix_shift, fl = P.fix_lo;
-                    if constexpr (B) {
-                        const DevPlan &Q = W.plans[W.gpoly[g]];
-                        fs = Q.fix_shift;
-                        fl = Q.fix_lo;
-                    }
-                    fix_out(fs, fl, a[0], a[1], a[2], a[3], rc.eref, m, e);
-                    const int j = W.sperm[p];
-                    m_out[j] = m;
-                    e_out[j] = e;
-                    if constexpr (D) {
-                        const int ez = exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y)));
-                        fix_out(fs, fl, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
-                        md_out[j] = m;
-                        ed_out[j] = e;
+            PointRec rc;
+            int j = 0;
+            if (p < nvalid) {                          // requested with the slots
+                rc = W.srec[p];
+                j = W.sperm[p];
+            }
+            long long a[kAccWords] = {};
+            for (int w0 = gw.x; w0 <= gw.y; w0 += 4) add_slots<kAccWords>(W, gw.x, gw.y, w0, lane, a);
+            if (p < nvalid && rc.l / W.chunk != rc.r / W.chunk)
+                final_out<D, B>(P, W, g, rc, j, a, m_out, e_out, md_out, ed_out);
+        } else {
+            const int pid = u - nsplit;
+            int lo = 0, hi = nlong - 1;                // the first long group with s_pre > pid
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] > pid) hi = mid; else lo = mid + 1;
+            }
+            const int li = lo;
+            const int first = li > 0 ? s_pre[li - 1] : 0;
+            const int np = s_pre[li] - first;
+            const int g = s_lg[li];
+            const int2 gw = s_lgw[li];
+            const int wa = gw.x + (pid - first) * kLongPiece, wb = min(gw.y, wa + kLongPiece - 1);
+            long long a[kAccWords] = {};
+            for (int w0 = wa; w0 <= wb; w0 += 4) add_slots<kAccWords>(W, gw.x, wb, w0, lane, a);
+            unsigned long long *acc =
+                reinterpret_cast<unsigned long long *>(W.lacc) + ((size_t)li * kWave + lane) * kSlotWords;
+#pragma unroll
+            for (int k = 0; k < kAccWords; ++k) atomicAdd(acc + k, (unsigned long long)a[k]);
+            __threadfence();                           // the sums before the count
+            int done = 0;
+            if (lane == 0) done = atomicAdd(W.lcnt + li, 1);
+            done = __shfl(done, 0);
+            if (done == np - 1) {                      // every other piece has added its sums
+                __threadfence();
+                const int p = g * kWave + lane;
+                if (p < nvalid) {
+                    const PointRec rc = W.srec[p];
+                    if (rc.l / W.chunk != rc.r / W.chunk) {
+#pragma unroll
+                        for (int k = 0; k < kAccWords; ++k)
+                            a[k] = (long long)__hip_atomic_load(acc + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        final_out<D, B>(P, W, g, rc, W.sperm[p], a, m_out, e_out, md_out, ed_out);
                     }
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -1340,6 +1465,7 @@ int g_num_cu = 0;
 // derivatives, adjoint
 enum TileKernel { kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2, kTileBatch = 3 };
 int g_window_blocks_per_cu[4] = {0, 0, 0, 0};
+int g_final_blocks_per_cu[3] = {0, 0, 0};   // k_finalize: values, derivatives, batch
 
 // wavefronts of a tile kernel: as many as are resident at once on the device
 // (the partition hands each one an equal share, so none may wait for a second
@@ -1347,6 +1473,14 @@ int g_window_blocks_per_cu[4] = {0, 0, 0, 0};
 int64_t window_waves(int kind) {
     const int b = g_window_blocks_per_cu[kind];
     return (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (b > 0 ? b : 1) * kWindowWaves;
+}
+
+// finalize workgroups: as many as are resident at once (a long group's
+// workgroup must not wait for a later round), at most one per split group
+unsigned final_blocks(int kind, int64_t n_waves) {
+    const int b = g_final_blocks_per_cu[kind];
+    const int64_t res = (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (b > 0 ? b : 1);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({n_waves - 1, res, kFinalBlocks}));
 }
 
 // instrumentation: event pairs around k_window
@@ -1376,6 +1510,15 @@ hipError_t device_setup() {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb[i], kern[i], kWindowThreads, 0);
     if (e != hipSuccess) return e;
     for (int i = 0; i < 4; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
+    const void *fin[3] = {reinterpret_cast<const void *>(k_finalize<false, false>),
+                          reinterpret_cast<const void *>(k_finalize<true, false>),
+                          reinterpret_cast<const void *>(k_finalize<false, true>)};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        int f = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, fin[i], kFinalThreads, 0);
+        g_final_blocks_per_cu[i] = f > 0 ? f : 1;
+    }
+    if (e != hipSuccess) return e;
     g_num_cu = ncu > 0 ? ncu : 256;
     return hipSuccess;
 }
@@ -1464,8 +1607,14 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     // as many window wavefronts as are resident, but no more than four per
     // group: a small evaluation then spreads its few tiles over few wavefronts
     w.n_waves = std::min<int64_t>(window_waves(kind), std::max<int64_t>(4 * G, 1));
+    // the finalize kernel holds the long groups in LDS
+    w.n_waves = std::min<int64_t>(w.n_waves, (int64_t)(kLongLds - 1) * kFinalShort);
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
+    const int64_t nlong = long_cap(nw_max);
+    w.lgroups = (int32_t *)take(sizeof(int32_t) * nlong);
+    w.lacc = (long long *)take(sizeof(long long) * kSlotWords * kWave * nlong);
+    w.lcnt = (int32_t *)take(sizeof(int32_t) * nlong);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
     w.n = n;
     w.tab_ib = tab_ib;
@@ -1600,7 +1749,7 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
             g_prof.pending.emplace_back(ev0, ev1);
         }
         if (W.n_waves > 1) {
-            const unsigned fb = (unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks);
+            const unsigned fb = final_blocks(deriv ? 1 : 0, W.n_waves);
             if (deriv) k_finalize<true, false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, md, ed, W);
             else k_finalize<false, false><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         }
@@ -1892,7 +2041,7 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         k_window<false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         if (W.n_waves > 1) {
-            const unsigned fb = (unsigned)std::min<int64_t>(W.n_waves - 1, kFinalBlocks);
+            const unsigned fb = final_blocks(2, W.n_waves);
             k_finalize<false, true><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         }
     }

@@ -64,12 +64,15 @@ struct EvalWs {
     int32_t *gml;                 //   largest window start,
     int32_t *gcost, *gcum;        //   work of its tiles and its prefix within its k_groups workgroup,
     int2 *gwave;                  //   first and last window wavefront owning its tiles
-    int32_t *split;               // groups owned by several window wavefronts (ctl[8] of them)
+    int32_t *split;               // groups owned by a few window wavefronts (ctl[8] of them)
+    int32_t *lgroups;             // groups owned by many (ctl[9] of them),
+    long long *lacc;              //   per such group 64 lanes x kSlotWords: the sum of its slots
+    int32_t *lcnt;                //   and the pieces of its owners summed so far
     int32_t *gblk_sum, *gblk_pre; // per k_groups workgroup: total work and (many groups) its scan
     int32_t *gseg_sum, *gseg_off; //   per 4096-entry segment of that scan
     int2 *wstart;                 // per window wavefront: first tile (group, chunk); n_waves + 1
     long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
-    int32_t *ctl;                 // [0] total tile work, [5] points in the count table, [8] split groups
+    int32_t *ctl;                 // [0] total tile work, [5] points in the count table, [8] [9] split groups
     int64_t n, n_groups, n_sort_blocks, n_waves;
     int32_t cost_shift;           // tile work is counted in units of (16 << cost_shift) steps
     int32_t tab_ib;               // bins per table-scan segment
