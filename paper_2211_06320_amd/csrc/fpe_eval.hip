@@ -580,51 +580,15 @@ constexpr int kSlotWords = 8;
 // share at most one wavefront, so an evaluation over n_waves wavefronts has
 // fewer than long_cap(n_waves) long groups.
 constexpr int kFinalShort = 8;
-constexpr int kLongPiece = 16;
+constexpr int kLongPiece = 32;
 constexpr int kLongLds = 2048;        // long groups the finalize kernel holds in LDS
 __host__ __device__ inline int long_cap(int64_t n_waves) { return (int)(n_waves / kFinalShort + 1); }
 
-__global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
-    __shared__ int32_t s_off[kPartLds];
+// window wavefront w's first tile (its share of the work starts at
+// ceil(w total / NW)), and the split-group list entry of the group it starts in
+__device__ __forceinline__ void partition_wave(const EvalWs &W, const BlockOffsets &bo, long long total, int nblk,
+                                               int w) {
     const int G = (int)W.n_groups, NW = (int)W.n_waves, C = W.chunk;
-    const int nblk = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
-    BlockOffsets bo{nullptr, W.gblk_pre, W.gseg_off};
-    long long total;
-    if (nblk <= kPartLds) {
-        int32_t carry = 0;
-        for (int s0 = 0; s0 < nblk; s0 += kSeg) {
-            int32_t v[4];
-            load4(W.gblk_sum + s0, min(kSeg, nblk - s0), v);
-            carry += block_scan4(v, s_off + s0, min(kSeg, nblk - s0), carry);
-        }
-        __syncthreads();
-        bo.lds = s_off;
-        total = carry;
-    } else {
-        total = W.ctl[0];
-    }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    {
-        // the finalize kernel's accumulators of long groups start at zero
-        const int64_t nacc = (int64_t)long_cap(NW) * kWave * kSlotWords / 2;
-        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-        longlong2 *acc = reinterpret_cast<longlong2 *>(W.lacc);
-        for (int64_t k = i; k < nacc; k += nthr) acc[k] = make_longlong2(0, 0);
-        if (i < long_cap(NW)) W.lcnt[i] = 0;
-    }
-    if (i < G) {
-        const int g = (int)i;
-        const int cost = W.gcost[g];
-        if (cost == 0 || total == 0) { W.gwave[g] = make_int2(-1, -1); return; }
-        const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
-        const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
-        const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
-        W.gwave[g] = gw;
-        if (gw.y - gw.x >= kFinalShort) W.lgroups[atomicAdd(W.ctl + 9, 1)] = g;
-        return;
-    }
-    if (i > (int64_t)G + NW) return;
-    const int w = (int)(i - G);
     const long long sw = total > 0 ? div_floor((long long)w * total + NW - 1, NW) : 0;
     if (w == NW || total == 0 || sw >= total) { W.wstart[w] = make_int2(G, 0); return; }
     // the last group starting at or before s_w: first its k_groups workgroup,
@@ -649,6 +613,62 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     if (st.x == g && div_floor(A * NW, total) == w - 1 &&
         div_floor((B - gc.last) * NW, total) - (w - 1) < kFinalShort)
         W.split[atomicAdd(W.ctl + 8, 1)] = g;
+}
+
+__global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
+    __shared__ int32_t s_off[kPartLds];
+    __shared__ int s_nl;                       // long groups found by this workgroup
+    __shared__ int s_li[1024];                 //   and their list indices
+    const int G = (int)W.n_groups, NW = (int)W.n_waves, C = W.chunk;
+    const int nblk = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    BlockOffsets bo{nullptr, W.gblk_pre, W.gseg_off};
+    long long total;
+    if (threadIdx.x == 0) s_nl = 0;
+    if (nblk <= kPartLds) {
+        int32_t carry = 0;
+        for (int s0 = 0; s0 < nblk; s0 += kSeg) {
+            int32_t v[4];
+            load4(W.gblk_sum + s0, min(kSeg, nblk - s0), v);
+            carry += block_scan4(v, s_off + s0, min(kSeg, nblk - s0), carry);
+        }
+        bo.lds = s_off;
+        total = carry;
+    } else {
+        total = W.ctl[0];
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < G) {
+        // group g's owners: the wavefronts whose shares hold its first and its
+        // last tile's start
+        const int g = (int)i;
+        const int cost = W.gcost[g];
+        if (cost == 0 || total == 0) {
+            W.gwave[g] = make_int2(-1, -1);
+        } else {
+            const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
+            const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
+            const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
+            W.gwave[g] = gw;
+            if (gw.y - gw.x >= kFinalShort) {
+                const int li = atomicAdd(W.ctl + 9, 1);
+                W.lgroups[li] = make_int4(g, gw.x, gw.y, 0);
+                s_li[atomicAdd(&s_nl, 1)] = li;
+            }
+        }
+    } else if (i <= (int64_t)G + NW) {
+        partition_wave(W, bo, total, nblk, (int)(i - G));
+    }
+    __syncthreads();
+    // the finalize kernel's accumulators and piece count of each long group
+    // found here start at zero
+    const int nl = s_nl;
+    for (int k = threadIdx.x; k < nl * (kWave * kSlotWords / 2); k += blockDim.x) {
+        const int li = s_li[k / (kWave * kSlotWords / 2)];
+        reinterpret_cast<longlong2 *>(W.lacc + (size_t)li * kWave * kSlotWords)[k % (kWave * kSlotWords / 2)] =
+            make_longlong2(0, 0);
+    }
+    if (threadIdx.x < nl) W.lcnt[s_li[threadIdx.x]] = 0;
 }
 
 // (g, c) with c < 0: the first tile of the first group at or after g with tiles
@@ -1142,9 +1162,9 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 // device-scope atomics; the piece that arrives last writes the outputs).  A
 // long group's slots, up to one per window wavefront, are so read by many
 // compute units at once.
-constexpr int kFinalThreads = 1024;
-constexpr int kFinalBlocks = 1024;    // workgroups of the finalize grid, at most
-static_assert(kLongLds == 2 * kFinalThreads, "the piece scan takes two long groups per thread");
+constexpr int kFinalThreads = 256;
+constexpr int kFinalBlocks = 4096;    // workgroups of the finalize grid, at most
+constexpr int kLongPer = kLongLds / kFinalThreads;   // long groups per thread in the piece scan
 
 // the outputs of one point of a split group from its summed partials
 template <bool D, bool B>
@@ -1171,11 +1191,10 @@ __device__ __forceinline__ void final_out(const DevPlan &P, const EvalWs &W, int
     }
 }
 
-// adds the slots of owners w0 .. min(w0 + 3, wy) of a group whose first owner
-// is wx to a; the loads are all issued before the first sum
-template <int kAccWords>
+// adds the slots of owners w0 .. min(w0 + kU - 1, wy) of a group whose first
+// owner is wx to a; the loads are all issued before the first sum
+template <int kAccWords, int kU>
 __device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w0, int lane, long long *a) {
-    constexpr int kU = 4;
     longlong2 x[kU][kAccWords / 2];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -1199,34 +1218,31 @@ __device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w
         }
 }
 
-__device__ __forceinline__ int long_pieces(int2 gw) { return (gw.y - gw.x + kLongPiece) / kLongPiece; }
+__device__ __forceinline__ int long_pieces(int4 v) { return (v.z - v.y + kLongPiece) / kLongPiece; }
 
 template <bool D, bool B>
-__global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
+__global__ __launch_bounds__(kFinalThreads, D ? 4 : 8) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out,
                                                             double2 *__restrict__ md_out,
                                                             long long *__restrict__ ed_out, EvalWs W) {
     constexpr int kAccWords = D ? 8 : 4;
     constexpr int nq = kFinalThreads / kWave;
-    __shared__ int s_lg[kLongLds];            // the long groups,
-    __shared__ int2 s_lgw[kLongLds];          //   their owner ranges
-    __shared__ int s_pre[kLongLds];           //   and the inclusive prefix of their pieces
+    __shared__ int s_pre[kLongLds];           // inclusive prefix of the long groups' pieces
     __shared__ int s_wsum[nq];
     const int lane = threadIdx.x % kWave, q = threadIdx.x / kWave;
     const int nsplit = W.ctl[8], nlong = W.ctl[9];
     const int nvalid = valid_points(W);
     int npieces = 0;
     if (nlong > 0) {                                   // the same for every thread
-        for (int i = threadIdx.x; i < nlong; i += kFinalThreads) {
-            const int g = W.lgroups[i];
-            s_lg[i] = g;
-            s_lgw[i] = W.gwave[g];
+        const int i0 = threadIdx.x * kLongPer;
+        int cnt[kLongPer];
+        int sum = 0;
+#pragma unroll
+        for (int e = 0; e < kLongPer; ++e) {
+            cnt[e] = i0 + e < nlong ? long_pieces(W.lgroups[i0 + e]) : 0;
+            sum += cnt[e];
         }
-        __syncthreads();
-        const int i0 = 2 * threadIdx.x;
-        const int c0 = i0 < nlong ? long_pieces(s_lgw[i0]) : 0;
-        const int c1 = i0 + 1 < nlong ? long_pieces(s_lgw[i0 + 1]) : 0;
-        int incl = c0 + c1;
+        int incl = sum;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
             const int t = __shfl_up(incl, d);
@@ -1234,35 +1250,30 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
         }
         if (lane == kWave - 1) s_wsum[q] = incl;
         __syncthreads();
-        int before = 0;
+        int run = incl - sum;
         for (int r = 0; r < nq; ++r) {
             const int ws = s_wsum[r];
-            if (r < q) before += ws;
+            if (r < q) run += ws;
             npieces += ws;
         }
-        const int excl = before + incl - c0 - c1;
-        if (i0 < nlong) s_pre[i0] = excl + c0;
-        if (i0 + 1 < nlong) s_pre[i0 + 1] = excl + c0 + c1;
+#pragma unroll
+        for (int e = 0; e < kLongPer; ++e) {
+            run += cnt[e];
+            if (i0 + e < nlong) s_pre[i0 + e] = run;
+        }
         __syncthreads();
     }
     // work items in wavefront order q * gridDim.x + blockIdx.x: neighbouring
     // items go to different workgroups
     const int nwork = nsplit + npieces;
     for (int u = q * (int)gridDim.x + (int)blockIdx.x; u < nwork; u += (int)gridDim.x * nq) {
+        // the owners [wa, wb] this item sums, of group g whose first owner is wx
+        int g, wx, wa, wb, li = -1, np = 0;
         if (u < nsplit) {
-            const int g = W.split[u];
+            g = W.split[u];
             const int2 gw = W.gwave[g];
-            const int p = g * kWave + lane;
-            PointRec rc;
-            int j = 0;
-            if (p < nvalid) {                          // requested with the slots
-                rc = W.srec[p];
-                j = W.sperm[p];
-            }
-            long long a[kAccWords] = {};
-            for (int w0 = gw.x; w0 <= gw.y; w0 += 4) add_slots<kAccWords>(W, gw.x, gw.y, w0, lane, a);
-            if (p < nvalid && rc.l / W.chunk != rc.r / W.chunk)
-                final_out<D, B>(P, W, g, rc, j, a, m_out, e_out, md_out, ed_out);
+            wx = wa = gw.x;
+            wb = gw.y;
         } else {
             const int pid = u - nsplit;
             int lo = 0, hi = nlong - 1;                // the first long group with s_pre > pid
@@ -1270,36 +1281,45 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize(DevPlan P, double2 *
                 const int mid = (lo + hi) >> 1;
                 if (s_pre[mid] > pid) hi = mid; else lo = mid + 1;
             }
-            const int li = lo;
+            li = lo;
             const int first = li > 0 ? s_pre[li - 1] : 0;
-            const int np = s_pre[li] - first;
-            const int g = s_lg[li];
-            const int2 gw = s_lgw[li];
-            const int wa = gw.x + (pid - first) * kLongPiece, wb = min(gw.y, wa + kLongPiece - 1);
-            long long a[kAccWords] = {};
-            for (int w0 = wa; w0 <= wb; w0 += 4) add_slots<kAccWords>(W, gw.x, wb, w0, lane, a);
+            np = s_pre[li] - first;
+            const int4 lg = W.lgroups[li];             // group, first and last owner
+            g = lg.x;
+            wx = lg.y;
+            wa = lg.y + (pid - first) * kLongPiece;
+            wb = min(lg.z, wa + kLongPiece - 1);
+        }
+        const int p = g * kWave + lane;
+        PointRec rc;
+        int j = 0;
+        if (p < nvalid) {                              // requested with the slots
+            rc = W.srec[p];
+            j = W.sperm[p];
+        }
+        long long a[kAccWords] = {};
+        for (int w0 = wa; w0 <= wb; w0 += 4) add_slots<kAccWords, 4>(W, wx, wb, w0, lane, a);
+        bool last = true;
+        if (li >= 0) {
+            // a piece of a long group: its sums go to the group's accumulator;
+            // the piece that arrives last writes the outputs
             unsigned long long *acc =
                 reinterpret_cast<unsigned long long *>(W.lacc) + ((size_t)li * kWave + lane) * kSlotWords;
 #pragma unroll
-            for (int k = 0; k < kAccWords; ++k) atomicAdd(acc + k, (unsigned long long)a[k]);
+            for (int t = 0; t < kAccWords; ++t) atomicAdd(acc + t, (unsigned long long)a[t]);
             __threadfence();                           // the sums before the count
             int done = 0;
             if (lane == 0) done = atomicAdd(W.lcnt + li, 1);
-            done = __shfl(done, 0);
-            if (done == np - 1) {                      // every other piece has added its sums
+            last = __shfl(done, 0) == np - 1;
+            if (last) {                                // every other piece has added its sums
                 __threadfence();
-                const int p = g * kWave + lane;
-                if (p < nvalid) {
-                    const PointRec rc = W.srec[p];
-                    if (rc.l / W.chunk != rc.r / W.chunk) {
 #pragma unroll
-                        for (int k = 0; k < kAccWords; ++k)
-                            a[k] = (long long)__hip_atomic_load(acc + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        final_out<D, B>(P, W, g, rc, W.sperm[p], a, m_out, e_out, md_out, ed_out);
-                    }
-                }
+                for (int t = 0; t < kAccWords; ++t)
+                    a[t] = (long long)__hip_atomic_load(acc + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        if (last && p < nvalid && rc.l / W.chunk != rc.r / W.chunk)
+            final_out<D, B>(P, W, g, rc, j, a, m_out, e_out, md_out, ed_out);
     }
 }
 
@@ -1480,7 +1500,8 @@ int64_t window_waves(int kind) {
 unsigned final_blocks(int kind, int64_t n_waves) {
     const int b = g_final_blocks_per_cu[kind];
     const int64_t res = (int64_t)(g_num_cu > 0 ? g_num_cu : 256) * (b > 0 ? b : 1);
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({n_waves - 1, res, kFinalBlocks}));
+    const int64_t need = (n_waves + kFinalThreads / kWave - 1) / (kFinalThreads / kWave);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({need, res, kFinalBlocks}));
 }
 
 // instrumentation: event pairs around k_window
@@ -1612,7 +1633,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     const int64_t nlong = long_cap(nw_max);
-    w.lgroups = (int32_t *)take(sizeof(int32_t) * nlong);
+    w.lgroups = (int4 *)take(sizeof(int4) * nlong);
     w.lacc = (long long *)take(sizeof(long long) * kSlotWords * kWave * nlong);
     w.lcnt = (int32_t *)take(sizeof(int32_t) * nlong);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
