@@ -94,7 +94,19 @@ __device__ __forceinline__ int valid_points(const EvalWs &W) {
 // [l, r] (eq. def:LRN) by two binary searches and a linear solve, the reference
 // exponent and the lambda bin.  Points with no window (z = 0, a non-finite z,
 // P == 0) get their value here and the bin kBins.  Returns the bin.
-__device__ __forceinline__ int bounds_point(const DevPlan &P, const double *hk, const double *hs,
+// The cover vertices (hk, hs) are read through an LDS-typed pointer when they
+// fit in LDS (ds_read, one short wait per search step) and through a global
+// pointer otherwise; through a generic pointer every search step would be a
+// flat load, waiting on both the memory and the LDS counter.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FPE_LDS_AS __attribute__((address_space(3)))
+#else
+#define FPE_LDS_AS
+#endif
+typedef const FPE_LDS_AS double *lds_table_t;
+
+template <class HP>
+__device__ __forceinline__ int bounds_point(const DevPlan &P, HP hk, HP hs,
                                             const double2 *__restrict__ z, int j, double2 *__restrict__ m_out,
                                             long long *__restrict__ e_out, double2 *__restrict__ md_out,
                                             long long *__restrict__ ed_out, int32_t *__restrict__ terms,
@@ -203,17 +215,19 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(DevPlan P, const doub
         for (int i = t; i < P.nh; i += kBoundsThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
     for (int i = t; i <= kBins; i += kBoundsThreads) hist[i] = 0;
     __syncthreads();
-    const double *hk = in_lds ? s_k : P.hull_k;
-    const double *hs = in_lds ? s_s : P.hull_s;
+    auto run = [&](auto hk, auto hs) {
 #pragma unroll
-    for (int it = 0; it < kPerThread; ++it) {
-        const int j = b * kSortPoints + it * kBoundsThreads + t;
-        if (j < n) {
-            const int key = bounds_point(P, hk, hs, z, j, m_out, e_out, md_out, ed_out, terms, win, W);
-            const int rank = atomicAdd(&hist[key], 1);  // LDS
-            W.keyrank[j] = key * kSortPoints + rank;
+        for (int it = 0; it < kPerThread; ++it) {
+            const int j = b * kSortPoints + it * kBoundsThreads + t;
+            if (j < n) {
+                const int key = bounds_point(P, hk, hs, z, j, m_out, e_out, md_out, ed_out, terms, win, W);
+                const int rank = atomicAdd(&hist[key], 1);  // LDS
+                W.keyrank[j] = key * kSortPoints + rank;
+            }
         }
-    }
+    };
+    if (in_lds) run((lds_table_t)s_k, (lds_table_t)s_s);
+    else run((const double *)P.hull_k, (const double *)P.hull_s);
     __syncthreads();
     for (int i = t; i <= kBins; i += kBoundsThreads) W.table[(size_t)b * (kBins + 1) + i] = hist[i];
 }
@@ -434,17 +448,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
     if (in_lds)
         for (int i = t; i < P.nh; i += kBatchThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
     __syncthreads();
-    const double *hk = in_lds ? s_k : P.hull_k;
-    const double *hs = in_lds ? s_s : P.hull_s;
     int np2 = 1;
     while (np2 < m) np2 <<= 1;
-    for (int j = t; j < np2; j += kBatchThreads) {
-        int key = INT_MAX;
-        if (j < m)
-            key = bounds_point(P, hk, hs, z, (int)(p0 + j), m_out, e_out, nullptr, nullptr, terms, nullptr, W) *
-                      kBatchMaxPoints + j;
-        s_key[j] = key;
-    }
+    auto run = [&](auto hk, auto hs) {
+        for (int j = t; j < np2; j += kBatchThreads) {
+            int key = INT_MAX;
+            if (j < m)
+                key = bounds_point(P, hk, hs, z, (int)(p0 + j), m_out, e_out, nullptr, nullptr, terms, nullptr, W) *
+                          kBatchMaxPoints + j;
+            s_key[j] = key;
+        }
+    };
+    if (in_lds) run((lds_table_t)s_k, (lds_table_t)s_s);
+    else run((const double *)P.hull_k, (const double *)P.hull_s);
     __syncthreads();
     for (int k = 2; k <= np2; k <<= 1) {
         for (int h = k >> 1; h > 0; h >>= 1) {
