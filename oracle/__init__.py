@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
     L.ora_adjoint_coef.argtypes = [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64, ctypes.c_int64,
                                    _f64p, _i64p, _f64p, _i64p]
     L.ora_absum.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
+    L.ora_cancel_bound.argtypes = [ctypes.c_void_p, _f64p, _f64p, _f64p, _i64p, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int32)]
     _LIB = L
     return L
 
@@ -167,6 +169,20 @@ class OraclePlan:
                        nthreads or default_threads())
         return {"m": m.view(np.complex128), "e": e, "l": l, "r": r, "terms": t,
                 "dwin_m": dm, "dwin_e": de, "lambda": lam, "N": N}
+
+    def cancel_bound(self, z, N, m, e) -> np.ndarray:
+        """Upper bound of the cancelled bits c of eq. (def_prec_loss) per point,
+        max(0, floor(N) + 1 - s(v)) for the value v = m 2^e (int32; 0 where the
+        point has no window, INT32_MAX where v = 0); N as returned by eval."""
+        zri = _as_ri(np.atleast_1d(z))
+        n = zri.shape[0] // 2
+        Nv = np.ascontiguousarray(np.asarray(N, np.float64).reshape(n))
+        mri = _as_ri(np.atleast_1d(m))
+        ev = np.ascontiguousarray(np.asarray(e, np.int64).reshape(n))
+        out = np.zeros(n, np.int32)
+        lib().ora_cancel_bound(self._h, _ptr(zri, _f64p), _ptr(Nv, _f64p), _ptr(mri, _f64p),
+                               _ptr(ev, _i64p), n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return out
 
     def eval_deriv(self, z, nthreads: int | None = None) -> dict:
         """Q_lambda(z) and Q'_lambda(z) = sum over the kept terms of k a_k z^(k-1),

@@ -23,6 +23,8 @@
  *                     k a_k z^(k-1)                                      Newton's method, Section 7.2
  *   ora_adjoint_coef  grad_a[k] = sum over the points keeping k of      reverse mode of eq. (reducedQlambda)
  *                     g_j conj(z_j)^k                                    (linear in a; kept set held fixed)
+ *   ora_cancel_bound  max(0, floor(N) + 1 - s(v)) >= c, the cancelled   Theorem equivAlgo, eq. (def_prec_loss);
+ *                     bits of a value v standing for P(z)                eq. (shear), Section 4.2
  *
  * Precision: every decision that yields an integer (scales, hull, G_p, the
  * argmax, the window ends) is taken in exact integer arithmetic or in FP64,
@@ -703,6 +705,35 @@ void ora_absum(const double *coef, int64_t d, const double *z, int64_t n,
 {
     ora_job J = { 2, NULL, coef, d, z, 0, 0, dm, de, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
     ora_run(J, n, nthreads);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cancelled bits (Theorem equivAlgo, eq. (def_prec_loss), Section 4.3):      */
+/* c = 0 when |P(z)| >= M, else s(M) - s(P(z)), with M = max_j |a_j z^j|.     */
+/* By eq. (shear) (Section 4.2) s(a_j z^j) <= s(a_j) + j lambda + 1, and       */
+/* s(a_j) <= Ehat(j), so s(M) <= N + 1 and, s(M) being an integer,            */
+/* s(M) <= floor(N) + 1.  The reported count is the upper bound               */
+/* max(0, floor(N) + 1 - s(v)) for a value v = m 2^e standing for P(z) (the    */
+/* value the method returned); with the exact c it satisfies                   */
+/* c <= bound <= c + 2 when v = P(z), since s(M) >= N - 1 (the term at the     */
+/* vertex k_lambda).  Points without a window report 0: z = 0 (P(0) = a_0,     */
+/* so |P| >= M), P == 0, and a non-finite z.  v = 0 (every bit cancelled)      */
+/* reports INT32_MAX.  N is the oracle's FP64 N of ora_eval.                   */
+/* ------------------------------------------------------------------------- */
+void ora_cancel_bound(const ora_plan *P, const double *z, const double *N, const double *m,
+                      const int64_t *e, int64_t n, int32_t *out)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        const double zr = z[2 * j], zi = z[2 * j + 1];
+        if (P->nh == 0 || !isfinite(zr) || !isfinite(zi) || (zr == 0.0 && zi == 0.0)) {
+            out[j] = 0;
+            continue;
+        }
+        const int64_t sv = ora_scale1(m[2 * j], m[2 * j + 1]);
+        if (sv == ORA_NEG_INF) { out[j] = INT32_MAX; continue; }
+        const int64_t c = (int64_t)floor(N[j]) + 1 - (sv + e[j]);
+        out[j] = c > 0 ? (int32_t)(c < INT32_MAX ? c : INT32_MAX) : 0;
+    }
 }
 
 /* ------------------------------------------------------------------------- */

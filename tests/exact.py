@@ -27,6 +27,19 @@ def exact_scale(x: float, y: float):
     return sigma
 
 
+def exact_scale_pair(pair):
+    """s of a complex rational (re, im): sigma with 4^(sigma-1) <= |v|^2 < 4^sigma; None for zero."""
+    q = pair[0] * pair[0] + pair[1] * pair[1]
+    if q == 0:
+        return None
+    sigma = int(math.floor(0.5 * (math.log2(q.numerator) - math.log2(q.denominator)))) + 1
+    while not (Fr(4) ** (sigma - 1) <= q):
+        sigma -= 1
+    while not (q < Fr(4) ** sigma):
+        sigma += 1
+    return sigma
+
+
 def cplx_mul(a, b):
     return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
 

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 from exact import (concave_majorant, cover_vertices, cplx_mul, exact_deriv_subset, exact_poly, exact_scale,
-                   exact_sum_subset, frac_abs_log2, to_complex)
+                   exact_scale_pair, exact_sum_subset, frac_abs_log2, to_complex)
 from paper_2211_06320_amd import workloads
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -334,6 +334,113 @@ def test_target_relative_bound_with_cancellation():
                 assert lres <= -(p - cbits) - 2 + lp + 1e-9
                 checked += 1
     assert checked > 100
+
+
+def _exact_c(coeffs, z, Pz):
+    """The cancelled bits of eq. (def_prec_loss) exactly: 0 if |P(z)| >= M, else
+    s(M) - s(P(z)), M = max_j |a_j z^j| (scales of exact complex rationals)."""
+    zr = (Fr(float(z.real)), Fr(float(z.imag)))
+    t = (Fr(1), Fr(0))
+    sM = None
+    best = Fr(0)
+    for a in coeffs:
+        term = cplx_mul((Fr(float(a.real)), Fr(float(a.imag))), t)
+        q = term[0] ** 2 + term[1] ** 2
+        if q > best:
+            best, sM = q, exact_scale_pair(term)
+        t = cplx_mul(t, zr)
+    sP = exact_scale_pair(Pz)
+    if Pz[0] ** 2 + Pz[1] ** 2 >= best:
+        return 0
+    return sM - sP
+
+
+def _as_value(pair):
+    """A nonzero complex rational as a double mantissa pair and a binary exponent."""
+    shift = -int(math.floor(frac_abs_log2(pair)))
+    return to_complex(pair, shift), -shift
+
+
+def test_cancel_bound_brackets_exact_c():
+    """max(0, floor(N) + 1 - s(P)) >= c, and <= c + 2 (eq. def_prec_loss with
+    eq. shear: N - 1 <= s(M) <= floor(N) + 1), fed the exact P(z); exact rationals."""
+    rng = np.random.default_rng(321)
+    checked = tight = 0
+    for c in _random_tiny_polys(rng, 40):
+        z = _tiny_points(rng, 12)
+        P = oracle.precondition(c, 53)
+        r = P.eval(z)
+        for i, zi in enumerate(z):
+            if zi == 0:
+                continue
+            N = r["N"][i]
+            if abs(N - round(N)) < 1e-9:        # FP64 N on an integer: floor undecided
+                continue
+            Pz = exact_poly(c, zi)
+            if Pz[0] == 0 and Pz[1] == 0:
+                continue
+            m, e = _as_value(Pz)
+            if exact_scale(m.real, m.imag) + e != exact_scale_pair(Pz):
+                continue                          # rounding reached the next power of two
+            cb = int(P.cancel_bound(np.array([zi]), [N], np.array([m]), [e])[0])
+            ce = _exact_c(c, zi, Pz)
+            assert ce <= cb <= ce + 2, (c, zi, ce, cb)
+            tight += cb == ce
+            checked += 1
+    assert checked > 300 and tight > checked // 4
+
+
+def test_cancel_bound_special_values():
+    """P = 1 + z: P(-1) = 0 (every bit cancelled), P(0) = a_0 (c = 0), a non-finite
+    z reports 0; z^d - 1 at rounded roots of unity: deep cancellation, bracketed
+    by the exact c; P == 0 reports 0."""
+    P = oracle.precondition(np.array([1, 1], complex), 53)
+    z = np.array([-1 + 0j, 0j, np.nan + 0j, np.inf + 1j])
+    r = P.eval(z)
+    cb = P.cancel_bound(z, r["N"], r["m"], r["e"])
+    assert cb[0] == 2 ** 31 - 1 and list(cb[1:]) == [0, 0, 0]
+    d = 12
+    c = np.zeros(d + 1, complex)
+    c[0], c[d] = -1, 1
+    P = oracle.precondition(c, 53)
+    z = np.exp(2j * np.pi * np.array([1, 5, 7]) / d)
+    r = P.eval(z)
+    for i, zi in enumerate(z):
+        Pz = exact_poly(c, zi)
+        m, e = _as_value(Pz)
+        cb = int(P.cancel_bound(np.array([zi]), [r["N"][i]], np.array([m]), [e])[0])
+        ce = _exact_c(c, zi, Pz)
+        assert ce > 40 and ce <= cb <= ce + 2
+    Z = oracle.precondition(np.zeros(4, complex), 53)
+    z = np.array([0.5 + 0.5j, 2.0 + 0j])
+    r = Z.eval(z)
+    assert list(Z.cancel_bound(z, r["N"], r["m"], r["e"])) == [0, 0]
+
+
+def test_cancel_bound_in_error_bound():
+    """The error bound of eq. (target) holds with the reported count in place of
+    c (it is an upper bound of c): |P - Q| <= 2^-(p - bound) - 2 |P|."""
+    rng = np.random.default_rng(77)
+    checked = 0
+    for c in _random_tiny_polys(rng, 30):
+        z = _tiny_points(rng, 10)
+        for p in (8, 24, 53):
+            P = oracle.precondition(c, p)
+            r = P.eval(z)
+            cb = P.cancel_bound(z, r["N"], r["m"], r["e"])
+            for i, zi in enumerate(z):
+                Pz = exact_poly(c, zi)
+                lp = frac_abs_log2(Pz)
+                if lp == -math.inf or zi == 0 or cb[i] == 2 ** 31 - 1:
+                    continue
+                ks = [k for k in range(r["l"][i], r["r"][i] + 1) if P.good()[k]]
+                Qz = exact_sum_subset(c, zi, ks)
+                lres = frac_abs_log2((Pz[0] - Qz[0], Pz[1] - Qz[1]))
+                if lres == -math.inf:
+                    continue
+                assert lres <= -(p - int(cb[i])) - 2 + lp + 1e-9
+                checked += 1
+    assert checked > 300
 
 
 def test_geometric_series_closed_forms():
