@@ -189,6 +189,26 @@ fpe_status fpe_eval_deriv(fpe_plan_t plan, const double *z_dev, int64_t n,
                           double *m_dev, int64_t *e_dev, double *md_dev, int64_t *ed_dev,
                           void *workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
+/* Upper bound of the cancelled bits c (Theorem equivAlgo, eq. (def_prec_loss):
+ * c = 0 if |P(z)| >= M, else s(M) - s(P(z)), M = max_k |a_k z^k|) for values
+ * v_j = m_j 2^{e_j} standing for P(z_j), e.g. fpe_eval's outputs:
+ *   bits_j = max(0, floor(N_j) + 1 - s(v_j)),  N_j = max over the cover of
+ *   Ehat(k) + lambda_j k (eq. defN), in FP64 as fpe_eval computes it.
+ * By eq. (shear) every term has s(a_k z^k) <= N + 1, so s(M) <= floor(N) + 1:
+ * bits_j >= c, and bits_j <= c + 2 when v_j = P(z_j).  With eq. (target) the
+ * returned value has at least p - bits_j - 2 correct leading bits (the report
+ * of correct bits the paper's library writes per point, Section 8).  s(v) is
+ * decided exactly; floor(N) in FP64 (lambda is FP64, as in fpe_eval).
+ *   z_dev          2n doubles: the points.
+ *   m_dev, e_dev   2n doubles and n int64: the values, normalised or not.
+ *   bits_dev       output: n int32.  0 where z_j = 0 (P(0) = a_0 exactly),
+ *                  z_j is not finite, or P == 0; INT32_MAX where v_j = 0.
+ * No workspace; enqueued on stream (no synchronisation).  Errors:
+ * FPE_ERR_INVALID_ARG (NULL plan, a NULL pointer with n > 0, n < 0 or
+ * n >= 2^31 - 1, z or m not 16-byte aligned), FPE_ERR_HIP. */
+fpe_status fpe_cancelled_bits(fpe_plan_t plan, const double *z_dev, int64_t n, const double *m_dev,
+                              const int64_t *e_dev, int32_t *bits_dev, hipStream_t stream);
+
 /* One Newton step per point (Section 7.2, eq. newton): z_out = z - Q / Q' with
  * Q and Q' from fpe_eval_deriv (written to m, e, md, ed as there; the caller
  * keeps them).  The quotient is taken on the mantissas and scaled by

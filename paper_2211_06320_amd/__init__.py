@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.fpe_batch_autotune.argtypes = [vp, vp, vp, vp, vp, sz, vp, P(i32)]
     L.fpe_eval_adjoint.restype = i32
     L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_cancelled_bits.restype = i32
+    L.fpe_cancelled_bits.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.fpe_horner_eval.restype = i32
     L.fpe_horner_eval.argtypes = [vp, i64, vp, i64, vp, vp, vp]
     L.fpe_profile_enable.restype = i32
@@ -286,6 +288,24 @@ class Plan:
         _check(lib().fpe_newton_step(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
                                      ed.data_ptr(), zn.data_ptr(), ws, nb, _stream(stream)))
         return zn, m, e, md, ed
+
+    def cancelled_bits(self, z, m=None, e=None, stream=None):
+        """Upper bound of the cancelled bits c of eq. (def_prec_loss) per point for
+        the values m 2^e (this plan's eval of z when not given): int32 tensor,
+        max(0, floor(N) + 1 - s(m 2^e)); at least p - bits - 2 leading bits of
+        the value are correct."""
+        torch = _torch()
+        z = _dev_complex(z, "z")
+        if m is None or e is None:
+            m, e = self.eval(z, stream=stream)
+        m = _dev_complex(m, "m")
+        if m.shape != z.shape or e.shape != z.shape or e.dtype != torch.int64 or e.device != z.device:
+            raise ValueError("m and e must be [n] complex128 and int64 on the device of z")
+        e = e.contiguous()
+        bits = torch.empty(z.shape[0], dtype=torch.int32, device=z.device)
+        _check(lib().fpe_cancelled_bits(self._h, z.data_ptr(), z.shape[0], m.data_ptr(), e.data_ptr(),
+                                        bits.data_ptr(), _stream(stream)))
+        return bits
 
     def adjoint(self, z, g, md=None, ed=None, grad_a: bool = True, grad_z: bool = True, stream=None):
         """Reverse mode of Q_lambda for upstream gradients g (complex convention:

@@ -1,8 +1,9 @@
 // Evaluation phase (Algorithm A_p, second block; Section 5.2 of arXiv 2211.06320)
 // on gfx950.
 //
-// One evaluation is a chain of short kernels on one stream, without
-// device-scope atomics on the data path:
+// One evaluation is a chain of short kernels on one stream; device-scope
+// atomics serve only list counters and the integer accumulators of the few
+// long split groups (exact sums, so their order does not matter):
 //
 //   k_bounds     per point: lambda = log2|z| (eq. defLambda), k_lambda and
 //                N = max(Ehat + lambda Id) (eq. defN) by binary search over the
@@ -18,18 +19,22 @@
 //   k_groups     per group of 64 consecutive sorted points (one wavefront):
 //                the union of their windows and the work of its C-term chunks
 //   k_scan_seg, k_partition   an equal-work partition of the (group, chunk)
-//                tiles over the window kernel's wavefronts
+//                tiles over the window kernel's wavefronts, and the lists of
+//                groups split across wavefronts (few owners / many owners)
 //   k_window     every wavefront runs its contiguous range of tiles.  The 64
 //                lanes of a tile share the coefficient stream (wave-uniform
-//                index, scalar loads prefetched one batch ahead) and each runs
+//                index, scalar loads two batches in flight) and each runs
 //                Horner's rule over its own part of the chunk; lanes whose
 //                window is shorter are masked only at the ragged ends.  Then
 //                z^lo by double-double binary powering with an exact exponent.
 //                A window inside one chunk is written out at once; the chunk
 //                partials of longer windows are summed exactly in fixed point,
-//                in registers while the wavefront stays on the group
+//                in LDS while the wavefront stays on the group, in the
+//                wavefront's slots otherwise
 //   k_finalize   windows of groups split across wavefronts: the sum of the
-//                wavefronts' fixed-point partials, to (mantissa, exponent)
+//                wavefronts' fixed-point partials, to (mantissa, exponent); a
+//                wavefront per group with a few owners, 32-owner pieces with
+//                atomic accumulation for groups with many
 //
 // Every chunk partial is computed the same way whichever wavefront runs it and
 // fixed-point sums are exact, so results do not depend on the partition or on
@@ -94,6 +99,28 @@ __device__ __forceinline__ int valid_points(const EvalWs &W) {
 // [l, r] (eq. def:LRN) by two binary searches and a linear solve, the reference
 // exponent and the lambda bin.  Points with no window (z = 0, a non-finite z,
 // P == 0) get their value here and the bin kBins.  Returns the bin.
+// lambda = log2|z| (eq. defLambda) for a finite nonzero z: |z| = |w| 2^ez with
+// max(|Re w|, |Im w|) in [1/2, 1) (an exact rescaling), so no square overflows
+__device__ __forceinline__ double log2_abs(double2 zz) {
+    const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
+    const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
+    return (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
+}
+
+// k_lambda (eq. defN): Ehat + lambda Id is concave, so its vertex values rise
+// then fall; the leftmost maximiser is the first vertex whose next value is
+// not larger (binary search over the nh >= 1 cover vertices)
+template <class HP>
+__device__ __forceinline__ int cover_argmax(int nh, HP hk, HP hs, double lam) {
+    int lo = 0, hi = nh - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
+        if (dF <= 0.0) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // The cover vertices (hk, hs) are read through an LDS-typed pointer when they
 // fit in LDS (ds_read, one short wait per search step) and through a global
 // pointer otherwise; through a generic pointer every search step would be a
@@ -128,19 +155,8 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, HP hk, HP hs,
         if (P.v == 0) { normalise(P.a0.x, P.a0.y, 0, mo, eo); cnt = 1; }
     } else {
         done = false;
-        const int ez = exp_of(fmax(fabs(zz.x), fabs(zz.y)));
-        const double xr = ldexp(zz.x, -ez), xi = ldexp(zz.y, -ez);
-        const double lam = (double)ez + 0.5 * log2(fma(xr, xr, xi * xi));
-        // k_lambda: Ehat + lambda Id is concave, so its vertex values rise
-        // then fall; the leftmost maximiser is the first vertex whose next
-        // value is not larger
-        int lo = 0, hi = nh - 1;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            double dF = (hs[mid + 1] - hs[mid]) + lam * (hk[mid + 1] - hk[mid]);
-            if (dF <= 0.0) hi = mid; else lo = mid + 1;
-        }
-        const int is = lo;
+        const double lam = log2_abs(zz);
+        const int is = cover_argmax(nh, hk, hs, lam);
         const double N = fma(lam, hk[is], hs[is]);
         const double L = N - (double)P.T;
         // left end: the crossing of the level L on the rising branch [0, is]
@@ -958,8 +974,13 @@ __device__ __forceinline__ SegPlan group_plan(const DevPlan &P, const EvalWs &W,
 
 __device__ __forceinline__ void fix_add(const SegPlan &P, double qr, double qi, long long E, long long eref,
                                         long long &a0, long long &a1, long long &a2, long long &a3) {
+    // (qr, qi) is not normalised: the table holds a_k 2^-coef_shift, so a
+    // partial of small terms under a large coef_shift has a mantissa far below
+    // 1 and needs a shift of up to about the coefficients' scale range (at most
+    // 2 (958 - T)).  The window bound keeps the result below 2^(fix_shift +
+    // bitlen(W) - 2) <= 2^58; the clamp only keeps ldexp's argument in range.
     long long sh = E - eref + P.fix_shift;
-    sh = sh < -2200 ? -2200 : (sh > 200 ? 200 : sh);
+    sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
     const double xr = ldexp(qr, (int)sh), xi = ldexp(qi, (int)sh);
     const double hr0 = trunc(xr), hi0 = trunc(xi);
     a0 += (long long)hr0;
@@ -1580,6 +1601,54 @@ __global__ __launch_bounds__(256) void k_newton(const double2 *__restrict__ z, i
     z_out[j] = make_double2(zz.x - qr, zz.y - qi);
 }
 
+// Upper bound of the cancelled bits c of eq. (def_prec_loss) (Theorem
+// equivAlgo): every term has s(a_k z^k) <= s(a_k) + k lambda + 1 (eq. shear)
+// <= Ehat(k) + k lambda + 1 <= N + 1, so s(M) <= floor(N) + 1 for
+// M = max_k |a_k z^k|, and c <= max(0, floor(N) + 1 - s(v)) for the value
+// v = m 2^e standing for P(z).  lambda and N as k_bounds computes them, s(v)
+// exactly.  0 where the point has no window (z = 0, where P(0) = a_0 and
+// |P| >= M; a non-finite z; P == 0); INT32_MAX where v = 0.
+constexpr int kCancelThreads = 1024;
+constexpr int kCancelPer = 2;                   // points per thread
+
+__global__ __launch_bounds__(kCancelThreads) void k_cancel(DevPlan P, const double2 *__restrict__ z, int n,
+                                                           const double2 *__restrict__ m,
+                                                           const long long *__restrict__ e,
+                                                           int32_t *__restrict__ out) {
+    __shared__ double s_k[kHullLds];
+    __shared__ double s_s[kHullLds];
+    const int t = threadIdx.x;
+    const bool in_lds = P.nh <= kHullLds;
+    if (in_lds)
+        for (int i = t; i < P.nh; i += kCancelThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+    __syncthreads();
+    auto run = [&](auto hk, auto hs) {
+#pragma unroll
+        for (int it = 0; it < kCancelPer; ++it) {
+            const int j = (blockIdx.x * kCancelPer + it) * kCancelThreads + t;
+            if (j >= n) continue;
+            const double2 zz = z[j];
+            int32_t c = 0;
+            if (P.nh > 0 && isfinite(zz.x) && isfinite(zz.y) && (zz.x != 0.0 || zz.y != 0.0)) {
+                const double2 v = m[j];
+                const int32_t sv = scale_exact(v.x, v.y);
+                if (sv == kNegInfScale) {
+                    c = INT32_MAX;
+                } else {
+                    const double lam = log2_abs(zz);
+                    const int is = cover_argmax(P.nh, hk, hs, lam);
+                    const double N = fma(lam, hk[is], hs[is]);
+                    const long long b = (long long)floor(N) + 1 - ((long long)sv + e[j]);
+                    c = b <= 0 ? 0 : (b >= INT32_MAX ? INT32_MAX : (int32_t)b);
+                }
+            }
+            out[j] = c;
+        }
+    };
+    if (in_lds) run((lds_table_t)s_k, (lds_table_t)s_s);
+    else run((const double *)P.hull_k, (const double *)P.hull_s);
+}
+
 }  // namespace
 
 // Smallest cost unit shift for which the total tile work of n points fits the
@@ -1848,6 +1917,23 @@ extern "C" fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int6
         reinterpret_cast<const double2 *>(z_dev), (int)n, reinterpret_cast<const double2 *>(m_dev),
         reinterpret_cast<const long long *>(e_dev), reinterpret_cast<const double2 *>(md_dev),
         reinterpret_cast<const long long *>(ed_dev), reinterpret_cast<double2 *>(z_out_dev));
+    FPE_HIP_CHECK(hipGetLastError());
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_cancelled_bits(fpe_plan_t plan, const double *z_dev, int64_t n, const double *m_dev,
+                                         const int64_t *e_dev, int32_t *bits_dev, hipStream_t stream) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
+    if (n == 0) { set_error(""); return FPE_OK; }
+    if (!z_dev || !m_dev || !e_dev || !bits_dev) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(z_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(m_dev) % 16 != 0)
+        return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
+    const int64_t per = (int64_t)kCancelThreads * kCancelPer;
+    k_cancel<<<(unsigned)((n + per - 1) / per), kCancelThreads, 0, stream>>>(
+        plan->dev, reinterpret_cast<const double2 *>(z_dev), (int)n, reinterpret_cast<const double2 *>(m_dev),
+        reinterpret_cast<const long long *>(e_dev), bits_dev);
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");
     return FPE_OK;

@@ -123,6 +123,36 @@ __host__ __device__ __forceinline__ dd2 fast_two_sum(double a, double b) {
 // frexp-style exponent: x = f 2^k with |f| in [1/2, 1); x != 0 and finite
 __host__ __device__ __forceinline__ int exp_of(double x) { return ilogb(x) + 1; }
 
+// s(x + iy) exactly.  With a = max(|x|, |y|) = A 2^(m-53), b = min = B 2^(mb-53),
+// A, B < 2^53 integers and m = exponent of a (so s(a) = m), s(z) = m + 1 iff
+// x^2 + y^2 >= 4^m iff A^2 + B^2 4^(mb-m) >= 2^106.  The 106-bit squares are
+// formed from 64-bit halves; the floor of the shifted smaller square cannot
+// change the comparison because A^2 and 2^106 are integers.
+__device__ __forceinline__ int32_t scale_exact(double x, double y) {
+    double ax = fabs(x), ay = fabs(y);
+    double a = fmax(ax, ay), b = fmin(ax, ay);
+    if (a == 0.0) return kNegInfScale;
+    int m = exp_of(a);
+    unsigned long long A = (unsigned long long)ldexp(a, 53 - m);
+    unsigned long long ahi = __umul64hi(A, A), alo = A * A;
+    unsigned long long bhi = 0, blo = 0;
+    if (b != 0.0) {
+        int mb = exp_of(b);
+        int sh = 2 * (m - mb);
+        if (sh < 128) {
+            unsigned long long B = (unsigned long long)ldexp(b, 53 - mb);
+            unsigned long long h = __umul64hi(B, B), l = B * B;
+            if (sh >= 64) { l = h >> (sh - 64); h = 0; }
+            else if (sh > 0) { l = (l >> sh) | (h << (64 - sh)); h >>= sh; }
+            bhi = h; blo = l;
+        }
+    }
+    unsigned long long lo = alo + blo;
+    unsigned long long hi = ahi + bhi + (lo < alo ? 1ull : 0ull);
+    // 2^106 = bit 42 of the high word
+    return (hi >= (1ull << 42)) ? m + 1 : m;
+}
+
 // complex double-double with a separate binary exponent
 struct CDD { double rh, rl, ih, il; };
 

@@ -213,6 +213,27 @@ def test_wide_dynamic_range(fpe, kind):
     say(f"  max scaled error {worst:.3e}")
 
 
+def test_many_cover_vertices(fpe):
+    """600 cover vertices (nonzero a_k at k = i(i+1)/2 with s(a_k) = i, slopes
+    1/(i+1)), more than fit in LDS: the bounds kernel searches the cover in
+    global memory; plan, windows, term counts and values against the oracle."""
+    i = np.arange(600)
+    k = i * (i + 1) // 2
+    c = np.zeros(k[-1] + 1, complex)
+    c[k] = 1.5 * np.exp2(i - 1.0) * np.exp(1j * i)
+    z = np.concatenate([workloads.spherical_points(1500, 29), 2.0 ** np.linspace(-1, 1, 500)])
+    say(f"eval 600-vertex cover d={k[-1]} n={len(z)}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    ref = assert_plan_matches(plan, c, 53)
+    assert plan.info().n_hull == 600
+    r = ref.eval(z)
+    same = assert_windows(w, r)
+    assert np.array_equal(t[same], r["terms"][same])
+    assert_normalised(m, e)
+    worst = assert_values(m, e, c, z)
+    say(f"  max scaled error {worst:.3e}")
+
+
 def test_worked_example_windows(fpe):
     """The degree-10 example of Section 4.2 at p = 6, through the GPU plan and windows."""
     c = np.array([2.0 ** x for x in [-3, 5, -4, 15, 13, -5, 26, 15, 29, 29, 17]], complex)
