@@ -36,6 +36,9 @@
 //                wavefront per group with a few owners, 32-owner pieces with
 //                atomic accumulation for groups with many
 //
+// fpe_cancelled_bits (k_cancel) reports, per point and for a value standing
+// for P(z), an upper bound of the cancelled bits c of eq. (def_prec_loss).
+//
 // Every chunk partial is computed the same way whichever wavefront runs it and
 // fixed-point sums are exact, so results do not depend on the partition or on
 // which points share a wavefront.  The paper only suggests ordering points by
