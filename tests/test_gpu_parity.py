@@ -234,6 +234,33 @@ def test_many_cover_vertices(fpe):
     say(f"  max scaled error {worst:.3e}")
 
 
+def test_extreme_scale_range(fpe):
+    """Good coefficients over 1700 binary orders (scales on a concave parabola
+    from -850 to 850, near the 2 (958 - T) a plan accepts): the coefficient
+    table spans most of the FP64 range, windows of thousands of terms cross
+    several chunks, and the chunk partials' fixed-point shifts span the range."""
+    d = 20_000
+    k = np.arange(d + 1)
+    sc = 850 - np.round(1700 * ((2.0 * k / d) - 1) ** 2)
+    c = np.exp2(sc - 0.5) * np.exp(1j * 0.37 * k)
+    rng = np.random.default_rng(41)
+    lam = rng.uniform(-0.2, 0.2, 1500)
+    z = np.concatenate([2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, 1500)),
+                        workloads.spherical_points(500, 43)])
+    for p in (53, 24):
+        say(f"eval scale range 1700, d={d} p={p} n={len(z)}")
+        plan, m, e, t, w = gpu_eval(fpe, c, z, p)
+        ref = assert_plan_matches(plan, c, p)
+        r = ref.eval(z)
+        same = assert_windows(w, r)
+        assert np.array_equal(t[same], r["terms"][same])
+        chunk = plan.info().chunk
+        assert ((w[:, 1] // chunk) - (w[:, 0] // chunk) >= 2).sum() > 500
+        assert_normalised(m, e)
+        worst = assert_values(m, e, c, z, tol=TOL if p == 53 else 2.0 ** -18)
+        say(f"  max scaled error {worst:.3e}")
+
+
 def test_worked_example_windows(fpe):
     """The degree-10 example of Section 4.2 at p = 6, through the GPU plan and windows."""
     c = np.array([2.0 ** x for x in [-3, 5, -4, 15, 13, -5, 26, 15, 29, 29, 17]], complex)
