@@ -94,6 +94,19 @@ def test_deriv_wide_dynamic_range(fpe, kind):
     check(fpe, c, z, label=kind)
 
 
+def test_deriv_extreme_scale_range(fpe):
+    """Good coefficients over 1700 binary orders (scales on a concave parabola),
+    windows across several chunks: the fixed-point shifts of Q and Q' partials
+    span the coefficient table's range."""
+    d = 20_000
+    k = np.arange(d + 1)
+    sc = 850 - np.round(1700 * ((2.0 * k / d) - 1) ** 2)
+    c = np.exp2(sc - 0.5) * np.exp(1j * 0.37 * k)
+    rng = np.random.default_rng(47)
+    z = 2.0 ** rng.uniform(-0.2, 0.2, 1500) * np.exp(1j * rng.uniform(0, 2 * np.pi, 1500))
+    check(fpe, c, z, label="scale range 1700")
+
+
 def test_deriv_full_size(fpe):
     wl = workloads.workload("uniform_d1e6")
     check(fpe, wl.coeffs, wl.points, sample=400, label="d=1e6 sample")
