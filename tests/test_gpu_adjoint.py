@@ -136,6 +136,16 @@ def test_adjoint_wide_dynamic_range(fpe, kind):
     check(fpe, c, z, scaled_g(c, z, 66), kind)
 
 
+def test_adjoint_extreme_scale_range(fpe):
+    """Good coefficients over 1700 binary orders, windows across several chunks."""
+    d = 20_000
+    k = np.arange(d + 1)
+    c = np.exp2(850 - np.round(1700 * ((2.0 * k / d) - 1) ** 2) - 0.5) * np.exp(1j * 0.37 * k)
+    rng = np.random.default_rng(67)
+    z = 2.0 ** rng.uniform(-0.2, 0.2, 1500) * np.exp(1j * rng.uniform(0, 2 * np.pi, 1500))
+    check(fpe, c, z, scaled_g(c, z, 68), "scale range 1700")
+
+
 def test_adjoint_full_size_sample(fpe):
     """d = 10^6 and its 10^6 points, in the launch configuration of the
     benchmark; g is nonzero on 96 sampled points (every other point adds exact

@@ -82,6 +82,36 @@ def test_batched_matches_single_and_oracle(fpe):
     assert worst <= TOL
 
 
+def test_batched_extreme_plans(fpe):
+    """A batch whose polynomials include a 600-vertex cover (searched in global
+    memory) and good coefficients over 1700 binary orders, beside ordinary ones:
+    bit for bit the single-plan results, and within tolerance of the oracle."""
+    i = np.arange(600)
+    k = i * (i + 1) // 2
+    many = np.zeros(k[-1] + 1, complex)
+    many[k] = 1.5 * np.exp2(i - 1.0) * np.exp(1j * i)
+    d = 20_000
+    kk = np.arange(d + 1)
+    wide = np.exp2(850 - np.round(1700 * ((2.0 * kk / d) - 1) ** 2) - 0.5) * np.exp(1j * 0.37 * kk)
+    rng = np.random.default_rng(61)
+    near = lambda n, s: 2.0 ** rng.uniform(-s, s, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    coeffs = [workloads.uniform_coeffs(300, 5), many, wide, workloads.uniform_coeffs(2000, 6)]
+    points = [workloads.spherical_points(200, 71), near(1500, 0.2), near(1500, 0.2), near(900, 0.01)]
+    say("batch with a 600-vertex cover and a 1700-bit scale range")
+    plans, offs, zall, m, e, t = run_batch(fpe, coeffs, points)
+    worst = 0.0
+    for j, (c, z) in enumerate(zip(coeffs, points)):
+        sl = slice(offs[j], offs[j + 1])
+        m1, e1, t1, _ = plans[j].eval(to_dev(z), terms=True, window=True)
+        assert np.array_equal(m[sl].view(np.float64), m1.cpu().numpy().view(np.float64)), j
+        assert np.array_equal(e[sl], e1.cpu().numpy()) and np.array_equal(t[sl], t1.cpu().numpy()), j
+        ref = oracle.precondition(c, 53).eval(z)
+        err = oracle.scaled_error(m[sl], e[sl], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+        worst = max(worst, float(err.max(initial=0.0)))
+    say(f"  max scaled error {worst:.3e}")
+    assert worst <= TOL
+
+
 def test_batched_workload_4096(fpe):
     coeffs, points = workloads.batched_workload()
     plans, offs, zall, m, e, t = run_batch(fpe, coeffs, points)
