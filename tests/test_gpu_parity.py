@@ -351,6 +351,30 @@ def test_horner_baseline(fpe):
 
 
 # ----------------------------------------------------------------------------- full size
+@pytest.mark.parametrize("d,n", [(1_000_000, 1 << 24), (1 << 24, 1 << 20)])
+def test_beyond_bench_sizes(fpe, d, n):
+    """Past the benchmarked sizes: 2^24 points against d = 10^6, and a degree of
+    2^24 against 2^20 points.  Every point: normalised outputs and term counts in
+    range; a seeded sample (with the longest windows): windows, term counts and
+    values against the oracle (its window sum at p = 116)."""
+    c = workloads.uniform_coeffs(d, 91)
+    z = workloads.spherical_points(n, 92)
+    say(f"eval d={d} n={n}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    assert_normalised(m, e)
+    assert (t >= 1).all() and (t <= d + 1).all()
+    rng = np.random.default_rng(93)
+    idx = np.unique(np.concatenate([rng.choice(n, 600, replace=False), np.argsort(w[:, 0] - w[:, 1])[:10]]))
+    zs = z[idx]
+    ref = oracle.precondition(c, 53).eval(zs)
+    same = assert_windows(w[idx], ref, 0.99)
+    assert np.array_equal(t[idx][same], ref["terms"][same])
+    wide = oracle.precondition(c, 116).eval(zs)
+    err = oracle.scaled_error(m[idx], e[idx], wide["m"], wide["e"], wide["dwin_m"], wide["dwin_e"])
+    say(f"  max scaled error on {len(idx)} sampled points {err.max():.3e}")
+    assert err.max() <= TOL
+
+
 def test_full_size_d1e6(fpe):
     """d = 10^6, 10^6 spherical points, in the launch configuration the bench times.
 
