@@ -439,14 +439,17 @@ constexpr int kGroupsPerBlock = 1024 / kWave;
 
 // ---- many polynomials in one evaluation (fpe_eval_batched)
 constexpr int kBatchMaxPoints = 4096;   // points of one polynomial of a batch (sorted by one workgroup)
-constexpr int kBatchThreads = 1024;
+constexpr int kBatchThreads = 256;
+constexpr int kBatchScanPer = (kBins + 1 + kBatchThreads - 1) / kBatchThreads;   // bins per thread in the scan
 
 // One workgroup per polynomial of a batch: the bounds of its points (as in
-// k_bounds, with its own cover in LDS), their order by lambda bin (a bitonic
-// sort in LDS of bin x kBatchMaxPoints + index; finished points have the bin
-// kBins and come last) and its slots of the sorted records: the records in that
-// order, then records without a window up to a whole number of groups, so that
-// no group mixes two polynomials.
+// k_bounds, with its own cover in LDS), their order by lambda bin (a counting
+// sort in LDS: a point's rank within its bin from an LDS counter, then a scan
+// of the bin counts; finished points have the bin kBins and come last; the
+// order within a bin is free, since results do not depend on which points
+// share a wavefront) and its slots of the sorted records: the records in that
+// order, then records without a window up to a whole number of groups, so
+// that no group mixes two polynomials.
 __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__restrict__ plans,
                                                            const long long *__restrict__ pstart,
                                                            const int32_t *__restrict__ gstart,
@@ -455,8 +458,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
                                                            EvalWs W) {
     __shared__ double s_k[kHullLds];
     __shared__ double s_s[kHullLds];
-    __shared__ int32_t s_key[kBatchMaxPoints];
-    const int t = threadIdx.x;
+    __shared__ int32_t s_bin[kBins + 1];              // bin counts, then their exclusive prefix
+    __shared__ int32_t s_kr[kBatchMaxPoints];         // per point: bin x kBatchMaxPoints + rank in the bin
+    __shared__ int32_t s_wsum[kBatchThreads / kWave];
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
     const int pidx = blockIdx.x;
     if (pidx == 0 && t < 64) W.ctl[t] = 0;            // totals and counters of the later kernels
     const DevPlan P = plans[pidx];
@@ -466,48 +471,61 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
     const bool in_lds = P.nh <= kHullLds;
     if (in_lds)
         for (int i = t; i < P.nh; i += kBatchThreads) { s_k[i] = P.hull_k[i]; s_s[i] = P.hull_s[i]; }
+    for (int i = t; i <= kBins; i += kBatchThreads) s_bin[i] = 0;
     __syncthreads();
-    int np2 = 1;
-    while (np2 < m) np2 <<= 1;
     auto run = [&](auto hk, auto hs) {
-        for (int j = t; j < np2; j += kBatchThreads) {
-            int key = INT_MAX;
-            if (j < m)
-                key = bounds_point(P, hk, hs, z, (int)(p0 + j), m_out, e_out, nullptr, nullptr, terms, nullptr, W) *
-                          kBatchMaxPoints + j;
-            s_key[j] = key;
+        for (int j = t; j < m; j += kBatchThreads) {
+            const int key = bounds_point(P, hk, hs, z, (int)(p0 + j), m_out, e_out, nullptr, nullptr, terms, nullptr, W);
+            s_kr[j] = key * kBatchMaxPoints + atomicAdd(&s_bin[key], 1);   // LDS
         }
     };
     if (in_lds) run((lds_table_t)s_k, (lds_table_t)s_s);
     else run((const double *)P.hull_k, (const double *)P.hull_s);
     __syncthreads();
-    for (int k = 2; k <= np2; k <<= 1) {
-        for (int h = k >> 1; h > 0; h >>= 1) {
-            for (int i = t; i < np2; i += kBatchThreads) {
-                const int o = i ^ h;
-                if (o > i) {
-                    const int a = s_key[i], b = s_key[o];
-                    if ((a > b) == ((i & k) == 0)) { s_key[i] = b; s_key[o] = a; }
-                }
-            }
-            __syncthreads();
+    // exclusive prefix of the bin counts: a run of consecutive bins per thread
+    {
+        const int i0 = t * kBatchScanPer;
+        int v[kBatchScanPer];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kBatchScanPer; ++k) {
+            v[k] = i0 + k <= kBins ? s_bin[i0 + k] : 0;
+            sum += v[k];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int x = __shfl_up(incl, d);
+            if (lane >= d) incl += x;
+        }
+        if (lane == kWave - 1) s_wsum[wave] = incl;
+        __syncthreads();
+        int run_ = incl - sum;
+        for (int r = 0; r < wave; ++r) run_ += s_wsum[r];
+#pragma unroll
+        for (int k = 0; k < kBatchScanPer; ++k) {
+            if (i0 + k <= kBins) s_bin[i0 + k] = run_;
+            run_ += v[k];
         }
     }
-    for (int q = t; q < ng * kWave; q += kBatchThreads) {
+    __syncthreads();
+    // the records in bin order (each thread moves the points it bounded), then
+    // records without a window up to whole groups
+    for (int j = t; j < m; j += kBatchThreads) {
+        const int kr = s_kr[j];
+        const size_t dst = (size_t)g0 * kWave + s_bin[kr / kBatchMaxPoints] + kr % kBatchMaxPoints;
+        W.srec[dst] = W.rec[p0 + j];
+        W.sperm[dst] = (int)(p0 + j);
+    }
+    for (int q = m + t; q < ng * kWave; q += kBatchThreads) {
         const size_t dst = (size_t)g0 * kWave + q;
-        if (q < m) {
-            const int j = s_key[q] % kBatchMaxPoints;
-            W.srec[dst] = W.rec[p0 + j];
-            W.sperm[dst] = (int)(p0 + j);
-        } else {
-            PointRec rc;
-            rc.z = make_double2(0.0, 0.0);
-            rc.l = 1;
-            rc.r = 0;
-            rc.eref = 0;
-            W.srec[dst] = rc;
-            W.sperm[dst] = -1;
-        }
+        PointRec rc;
+        rc.z = make_double2(0.0, 0.0);
+        rc.l = 1;
+        rc.r = 0;
+        rc.eref = 0;
+        W.srec[dst] = rc;
+        W.sperm[dst] = -1;
     }
 }
 
