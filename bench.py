@@ -188,6 +188,17 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
         return a.elapsed_time(b) / k
 
     eager_ms = timed(lambda: batch.eval(z, out=out), steps)
+    # kept terms (one untimed call with term counts) and the window kernel's
+    # own time (HIP events around its launches, a few eager calls)
+    kept = int(batch.eval(z, terms=True)[2].sum().item())
+    fpe.profile_read()
+    fpe.profile_enable(True)
+    for _ in range(3):
+        batch.eval(z, out=out)
+    torch.cuda.synchronize()
+    fpe.profile_enable(False)
+    win_ms, win_k = fpe.profile_read()
+    win_ms = win_ms / max(win_k, 1)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -209,13 +220,16 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
                                                      ref["dwin_e"]).max()))
     log(f"batch of {len(plans)} polynomials, {n} points: eager {eager_ms:.3f} ms, graph replay {graph_ms:.3f} ms, "
         f"per-polynomial loop {loop_ms:.1f} ms (chunk {chunk}); preconditioning {pre_ms:.0f} ms; "
-        f"max scaled error (16 polynomials) {worst:.2e}")
+        f"max scaled error (16 polynomials) {worst:.2e}; {kept} kept terms, window kernel {win_ms:.3f} ms "
+        f"({8 * kept / (win_ms * 1e-3) / 1e12:.2f} TFLOP/s in the kept terms' FMAs)")
     return {"workload": "batched_4096", "n_poly": len(plans), "n_points": n,
             "coefficients": int(sum(len(c) for c in coeffs)), "unit": "evaluations/s", "chunk": chunk,
             "eager": {"ms": eager_ms, "value": n / (eager_ms * 1e-3)},
             "graph_replay": {"ms": graph_ms, "value": n / (graph_ms * 1e-3)},
             "per_polynomial_loop": {"ms": loop_ms, "value": n / (loop_ms * 1e-3)},
-            "precondition_ms": pre_ms, "max_scaled_err_16_polys": worst}
+            "precondition_ms": pre_ms, "max_scaled_err_16_polys": worst,
+            "kept_terms": kept, "window_kernel_ms": win_ms,
+            "window_tflops_kept_terms": 8 * kept / (win_ms * 1e-3) / 1e12}
 
 
 def main() -> int:

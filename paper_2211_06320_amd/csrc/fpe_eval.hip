@@ -2183,7 +2183,17 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
         const int nblk_g = (int)((W.n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
         launch_groups(P, W, nblk_g, stream);
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (g_prof.on) {
+            FPE_HIP_CHECK(prof_event(&ev0));
+            FPE_HIP_CHECK(prof_event(&ev1));
+            FPE_HIP_CHECK(hipEventRecord(ev0, stream));
+        }
         k_window<false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        if (g_prof.on) {
+            FPE_HIP_CHECK(hipEventRecord(ev1, stream));
+            g_prof.pending.emplace_back(ev0, ev1);
+        }
         if (W.n_waves > 1) {
             const unsigned fb = final_blocks(2, W.n_waves);
             k_finalize<false, true><<<fb, kFinalThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
