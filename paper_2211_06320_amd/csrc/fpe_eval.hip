@@ -380,18 +380,26 @@ __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
-// (16 << cost_shift) steps.  A tile costs its steps plus a fixed part, plus the
-// binary powerings it runs, at about kPowSteps steps per bit of the exponent
-// (measured on gfx950): a full powering where some window of the group starts
-// in the chunk (at most the chunks up to the group's largest window start),
-// and an anchor every kAnchor chunks for the lanes that continue.  A group also
-// costs a fixed part once (records, w^C).  Middle tiles cost one of two
-// amounts, before and after the last window start, which lets the partition
-// locate a tile in O(1).
+// (16 << cost_shift) steps.  A tile costs its steps plus a fixed part, plus a
+// full binary powering where some window of the group starts in the chunk (at
+// most the chunks up to the group's largest window start), at kPowSteps steps
+// per bit of the exponent.  A tile the group's windows continue into costs
+// kContBitSteps per bit of the group's last index more: the chained power, its
+// anchors every kAnchor chunks, the fixed-point partials and the LDS state of
+// the continuing lanes.  A group's first tile costs a fixed part more
+// (records, w^C).  The weights were fitted to per-wavefront times measured on
+// gfx950 (start and end clocks of every window wavefront, against the model's
+// components over its tiles): with the earlier weights (10 steps per bit, an
+// anchor at 10 steps per bit every kAnchor chunks, 64 per group) the
+// wavefronts were busy for 60-70 % of the kernel's span, those on groups of
+// large |z| (windows starting near d) running longest.  Middle tiles cost one
+// of two amounts, before and after the last window start, which lets the
+// partition locate a tile in O(1).
 constexpr int kCostUnit = 16;
-constexpr int kPowSteps = 10;
+constexpr int kPowSteps = 17;
+constexpr int kContBitSteps = 25;
 constexpr int kTileSteps = 8;
-constexpr int kGroupSteps = 64;
+constexpr int kGroupSteps = 40;
 
 struct GroupCost {
     int clo, chi;              // first and last chunk of the group's union window
@@ -414,7 +422,7 @@ __device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C
     gc.chi = ghi / C;
     const int cl = gml / C;
     const int pow_start = kPowSteps * bit_length(gml);
-    const int pow_cont = kPowSteps * bit_length(ghi) / kAnchor;
+    const int pow_cont = kContBitSteps * bit_length(ghi);
     if (gc.chi == gc.clo) {
         gc.first = gc.last = cost_units(ghi - glo + 1 + kTileSteps + kGroupSteps + pow_start, shift);
         gc.ns = 0;
@@ -1687,7 +1695,7 @@ int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
     for (int sh = 0; sh <= 20; ++sh) {
         const int64_t u = (int64_t)kCostUnit << sh;
         auto units = [u](int64_t steps) { return (steps + u - 1) / u; };
-        const int64_t per_tile = units(chunk + kTileSteps + kGroupSteps + kPowSteps * 31 * 2);
+        const int64_t per_tile = units(chunk + kTileSteps + kGroupSteps + (kPowSteps + kContBitSteps) * 31);
         const int64_t bound = G * chunks * per_tile;
         if (bound < INT32_MAX) return sh;
     }
