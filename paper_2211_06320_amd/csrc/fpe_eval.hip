@@ -380,26 +380,31 @@ __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
-// (16 << cost_shift) steps.  A tile costs its steps plus a fixed part, plus a
-// full binary powering where some window of the group starts in the chunk (at
-// most the chunks up to the group's largest window start), at kPowSteps steps
-// per bit of the exponent.  A tile the group's windows continue into costs
-// kContBitSteps per bit of the group's last index more: the chained power, its
-// anchors every kAnchor chunks, the fixed-point partials and the LDS state of
-// the continuing lanes.  A group's first tile costs a fixed part more
-// (records, w^C).  The weights were fitted to per-wavefront times measured on
-// gfx950 (start and end clocks of every window wavefront, against the model's
-// components over its tiles): with the earlier weights (10 steps per bit, an
-// anchor at 10 steps per bit every kAnchor chunks, 64 per group) the
-// wavefronts were busy for 60-70 % of the kernel's span, those on groups of
-// large |z| (windows starting near d) running longest.  Middle tiles cost one
-// of two amounts, before and after the last window start, which lets the
-// partition locate a tile in O(1).
+// (16 << cost_shift) steps.  A tile costs its steps plus a fixed part by kind,
+// plus a full binary powering where some window of the group starts in the
+// chunk (at most the chunks up to the group's largest window start), at
+// kPowSteps steps per bit of the exponent.  The fixed parts: every tile
+// kTileSteps (the coefficient batches, the output); the first tile of a group
+// spanning several chunks kFirstSteps more (fixed-point partials); its last
+// tile kLastSteps more and its middle tiles kMidSteps + C/8 more (the chained
+// power, the partials and the LDS state of the continuing lanes, and a middle
+// tile's Horner steps running with every lane active); a tile the windows
+// continue into kAnchorBitSteps per bit of the group's last index more (the
+// anchors of the chained power every kAnchor chunks, spread over the tiles).
+// The weights were fitted to the time of every tile of the window kernel
+// measured on gfx950 (start and end clocks per tile, against its Horner
+// steps, powering bits and kind, with one contention factor per interval of
+// the kernel's span shared by all tiles in it): the steps of one wavefront
+// are the unit, and the fit explains 89-96 % of the tiles' variance.  Middle
+// tiles cost one of two amounts, before and after the last window start,
+// which lets the partition locate a tile in O(1).
 constexpr int kCostUnit = 16;
-constexpr int kPowSteps = 17;
-constexpr int kContBitSteps = 25;
-constexpr int kTileSteps = 8;
-constexpr int kGroupSteps = 40;
+constexpr int kPowSteps = 20;
+constexpr int kTileSteps = 40;
+constexpr int kFirstSteps = 50;
+constexpr int kLastSteps = 100;
+constexpr int kMidSteps = 143;
+constexpr int kAnchorBitSteps = 4;
 
 struct GroupCost {
     int clo, chi;              // first and last chunk of the group's union window
@@ -422,18 +427,20 @@ __device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C
     gc.chi = ghi / C;
     const int cl = gml / C;
     const int pow_start = kPowSteps * bit_length(gml);
-    const int pow_cont = kContBitSteps * bit_length(ghi);
+    const int anchor = kAnchorBitSteps * bit_length(ghi);
     if (gc.chi == gc.clo) {
-        gc.first = gc.last = cost_units(ghi - glo + 1 + kTileSteps + kGroupSteps + pow_start, shift);
+        gc.first = gc.last = cost_units(ghi - glo + 1 + kTileSteps + pow_start, shift);
         gc.ns = 0;
         gc.cs = gc.cn = 1;
         return gc;
     }
-    gc.first = cost_units(gc.clo * C + C - glo + kTileSteps + kGroupSteps + pow_start, shift);
-    gc.last = cost_units(ghi - gc.chi * C + 1 + kTileSteps + (gc.chi <= cl ? pow_start : 0) + pow_cont, shift);
+    gc.first = cost_units(gc.clo * C + C - glo + kTileSteps + kFirstSteps + pow_start, shift);
+    gc.last = cost_units(ghi - gc.chi * C + 1 + kTileSteps + kLastSteps + anchor + (gc.chi <= cl ? pow_start : 0),
+                         shift);
     gc.ns = max(0, min(cl, gc.chi - 1) - gc.clo);
-    gc.cs = cost_units(C + kTileSteps + pow_start + pow_cont, shift);
-    gc.cn = cost_units(C + kTileSteps + pow_cont, shift);
+    const int mid = C + C / 8 + kTileSteps + kMidSteps + anchor;
+    gc.cs = cost_units(mid + pow_start, shift);
+    gc.cn = cost_units(mid, shift);
     return gc;
 }
 
@@ -1695,7 +1702,8 @@ int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
     for (int sh = 0; sh <= 20; ++sh) {
         const int64_t u = (int64_t)kCostUnit << sh;
         auto units = [u](int64_t steps) { return (steps + u - 1) / u; };
-        const int64_t per_tile = units(chunk + kTileSteps + kGroupSteps + (kPowSteps + kContBitSteps) * 31);
+        const int64_t per_tile = units(chunk + chunk / 8 + kTileSteps + kFirstSteps + kLastSteps + kMidSteps +
+                                       (kPowSteps + kAnchorBitSteps) * 31);
         const int64_t bound = G * chunks * per_tile;
         if (bound < INT32_MAX) return sh;
     }

@@ -156,19 +156,26 @@ __device__ __forceinline__ int32_t scale_exact(double x, double y) {
 // complex double-double with a separate binary exponent
 struct CDD { double rh, rl, ih, il; };
 
+// Scales x by a power of two so that max(|Re|, |Im|) of its high words lies in
+// [1/2, 1) and adds the power to E; the low words are folded into the high
+// ones first (the products below leave them unnormalised).
 __host__ __device__ __forceinline__ void cdd_renorm(CDD &x, long long &E) {
     FPE_NO_CONTRACT
-    double m = fmax(fabs(x.rh), fabs(x.ih));
+    const dd2 r = two_sum(x.rh, x.rl), i = two_sum(x.ih, x.il);
+    double m = fmax(fabs(r.hi), fabs(i.hi));
     int k = exp_of(m);
-    x.rh = ldexp(x.rh, -k); x.rl = ldexp(x.rl, -k);
-    x.ih = ldexp(x.ih, -k); x.il = ldexp(x.il, -k);
+    x.rh = ldexp(r.hi, -k); x.rl = ldexp(r.lo, -k);
+    x.ih = ldexp(i.hi, -k); x.il = ldexp(i.lo, -k);
     E += k;
 }
 
-// x^2 for a complex double-double x.  The last sum of each component is a
-// Fast2Sum: exact when the first operand is the larger one, and otherwise
-// (heavy cancellation in Re x^2) off by at most an ulp of that small
-// component, far below 2^-100 |x|^2.
+// x^2 for a complex double-double x = (rh + rl) + i (ih + il).  The products
+// of high words are split exactly (TwoProd through fma) and the real part's
+// difference of squares by TwoSum; the cross terms with one low word are added
+// to the low words, the products of two low words dropped.  The low words are
+// left unnormalised: relative to |x|, each squaring at most doubles their size
+// and adds 2^-51, so j squarings after a renormalisation they stay below
+// 2^(j - 50) |x|, and the dropped terms below 2^(2 j - 100) |x|^2.
 __host__ __device__ __forceinline__ CDD cdd_sqr(const CDD &x) {
     FPE_NO_CONTRACT
     const double rh2 = x.rh + x.rh;                  // exact
@@ -179,18 +186,16 @@ __host__ __device__ __forceinline__ CDD cdd_sqr(const CDD &x) {
     double e2 = fma(x.ih, x.ih, -p2);
     e2 = fma(x.ih + x.ih, x.il, e2);
     dd2 s = two_sum(p1, -p2);
-    dd2 re = fast_two_sum(s.hi, s.lo + (e1 - e2));
     // 2 rh ih: (2 rh) ih, and 2 (rh il + rl ih)
     double q = rh2 * x.ih;
     double eq = fma(rh2, x.ih, -q);
     eq = fma(rh2, x.il, eq);
     eq = fma(x.rl + x.rl, x.ih, eq);
-    dd2 im = fast_two_sum(q, eq);
-    return {re.hi, re.lo, im.hi, im.lo};
+    return {s.hi, s.lo + (e1 - e2), q, eq};
 }
 
-// x * w for a complex double-double x and a complex double w (last sums as in
-// cdd_sqr)
+// x * w for a complex double-double x and a complex double w (low words as in
+// cdd_sqr: the product by w, |w| < 2^(1/2), leaves their size relative to |x|)
 __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, double wi) {
     FPE_NO_CONTRACT
     double p1 = x.rh * wr, e1 = fma(x.rh, wr, -p1);
@@ -198,14 +203,12 @@ __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, doubl
     double p2 = x.ih * wi, e2 = fma(x.ih, wi, -p2);
     e2 = fma(x.il, wi, e2);
     dd2 s = two_sum(p1, -p2);
-    dd2 re = fast_two_sum(s.hi, s.lo + (e1 - e2));
     double p3 = x.rh * wi, e3 = fma(x.rh, wi, -p3);
     e3 = fma(x.rl, wi, e3);
     double p4 = x.ih * wr, e4 = fma(x.ih, wr, -p4);
     e4 = fma(x.il, wr, e4);
     dd2 t = two_sum(p3, p4);
-    dd2 im = fast_two_sum(t.hi, t.lo + (e3 + e4));
-    return {re.hi, re.lo, im.hi, im.lo};
+    return {s.hi, s.lo + (e1 - e2), t.hi, t.lo + (e3 + e4)};
 }
 
 // w^n (n >= 0) for |Re w|, |Im w| < 1 with max in [1/2, 1): left-to-right binary
@@ -213,7 +216,10 @@ __host__ __device__ __forceinline__ CDD cdd_mul_d(const CDD &x, double wr, doubl
 // (from a renormalised value, whose modulus is in [1/2, 2^(1/2)), four
 // squarings with products by w keep the modulus within [2^-31, 2^8], far from
 // the FP64 range limits).  Returns the renormalised, rounded mantissa and adds
-// the binary exponent to E.  Relative error about (2 log2 n) 2^-100.
+// the binary exponent to E.  Each squaring drops at most 2^-92 |x|^2 (four
+// squarings after a renormalisation) and later squarings double a relative
+// error, so after k squarings the relative error is below 2^(k - 92) before
+// the final rounding: below 2^-62 for n < 2^31.
 __host__ __device__ __forceinline__ void cpow_dd(double wr, double wi, int n, double &pr, double &pi,
                                         long long &E) {
     if (n == 0) { pr = 1.0; pi = 0.0; return; }
