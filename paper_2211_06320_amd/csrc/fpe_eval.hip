@@ -667,9 +667,16 @@ __device__ __forceinline__ void partition_wave(const EvalWs &W, const BlockOffse
         if (bo.at(mid) <= sw) lo = mid; else hi = mid - 1;
     }
     const long long base = bo.at(lo);
-    int g = lo * kGroupsPerBlock;
-    const int gend = min(G, g + kGroupsPerBlock);
-    while (g + 1 < gend && base + W.gcum[g + 1] <= sw) ++g;
+    // offsets inside a workgroup do not decrease: g is g0 plus the number of
+    // the workgroup's later groups starting at or before s_w (independent
+    // loads, one memory latency instead of one per group)
+    const int g0 = lo * kGroupsPerBlock, ng = min(G - g0, kGroupsPerBlock);
+    int32_t cum[kGroupsPerBlock];
+#pragma unroll
+    for (int k = 1; k < kGroupsPerBlock; ++k) cum[k] = k < ng ? W.gcum[g0 + k] : 0;
+    int g = g0;
+#pragma unroll
+    for (int k = 1; k < kGroupsPerBlock; ++k) g += (k < ng && base + cum[k] <= sw) ? 1 : 0;
     const long long A = base + W.gcum[g], B = A + W.gcost[g];
     if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
     const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
