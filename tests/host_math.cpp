@@ -28,3 +28,12 @@ extern "C" void hm_chunk_start(double wr, double wi, int c, int C, double *pr, d
     fpe::cpow_chunk_start(wr, wi, c, C, zcr, zci, zce, *pr, *pi, e);
     *E = e;
 }
+
+// the renormalisation: low words folded into the high ones, then a power-of-two scaling
+extern "C" void hm_cdd_renorm(const double *x, double *out, long long *E) {
+    fpe::CDD r = {x[0], x[1], x[2], x[3]};
+    long long e = 0;
+    fpe::cdd_renorm(r, e);
+    out[0] = r.rh; out[1] = r.rl; out[2] = r.ih; out[3] = r.il;
+    *E = e;
+}

@@ -27,6 +27,7 @@ def hm(tmp_path_factory):
     L.hm_cdd_mul_d.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
     L.hm_chunk_start.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.hm_cdd_renorm.argtypes = [dp, dp, ctypes.POINTER(ctypes.c_longlong)]
     L.hm_cpow.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_longlong)]
@@ -34,12 +35,14 @@ def hm(tmp_path_factory):
 
 
 def test_cpow_dd_against_mpmath(hm):
-    """w^n with w normalised (max component in [1/2, 1)): relative error <= 2^-51 after rounding."""
+    """w^n with w normalised (max component in [1/2, 1)): relative error <= 2^-52
+    after rounding (each component rounded once; the double-double part stays
+    below 2^-62 for any int exponent)."""
     import mpmath
     mpmath.mp.prec = 256
     rng = np.random.default_rng(4)
     pr, pi, E = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
-    ns = [0, 1, 2, 3, 7, 64, 952, 1000, 4095, 999_999, 1 << 20, (1 << 30) + 12345]
+    ns = [0, 1, 2, 3, 7, 64, 952, 1000, 4095, 999_999, 1 << 20, (1 << 30) + 12345, (1 << 31) - 1]
     for _ in range(200):
         t = rng.uniform(0, 2 * np.pi)
         w = complex(np.cos(t), np.sin(t)) * rng.uniform(0.5, 1.41)
@@ -51,7 +54,7 @@ def test_cpow_dd_against_mpmath(hm):
             got = mpmath.mpc(pr.value, pi.value) * mpmath.mpf(2) ** E.value
             exact = mpmath.mpc(w.real, w.imag) ** n
             rel = abs(got - exact) / abs(exact)
-            assert rel <= 2.0 ** -51, (w, n, float(rel))
+            assert rel <= 2.0 ** -52, (w, n, float(rel))
             mx = max(abs(pr.value), abs(pi.value))
             assert n == 0 or 0.5 <= mx < 1.0
 
@@ -118,3 +121,41 @@ def test_chunk_start_powers_against_mpmath(hm):
             assert rel <= 3 * 8 * 2.0 ** -53, (w, c, rel)
             mx = max(abs(pr.value), abs(pi.value))
             assert c == 0 or 0.5 <= mx < 1.0        # w^0 is returned as 1
+
+
+def _mp(v):
+    import mpmath
+    return mpmath.mpc(mpmath.mpf(v[0]) + mpmath.mpf(v[1]), mpmath.mpf(v[2]) + mpmath.mpf(v[3]))
+
+
+def test_cdd_unnormalised_low_words(hm):
+    """Between renormalisations the powering leaves low words unnormalised, up
+    to 2^-46 |x| after four squarings: a square or a product by w then drops at
+    most the products of two low words, 2^-92 |x|^2, plus roundings far below
+    it; the renormalisation folds the low words in exactly and scales by a
+    power of two."""
+    import mpmath
+    mpmath.mp.prec = 300
+    rng = np.random.default_rng(9)
+    out = np.zeros(4)
+    E = ctypes.c_longlong()
+    dp = ctypes.POINTER(ctypes.c_double)
+    for _ in range(3000):
+        x = _cdd(rng)
+        mag = max(abs(x[0]), abs(x[2]))
+        x[1] = rng.uniform(-1, 1) * 2.0 ** -46 * mag
+        x[3] = rng.uniform(-1, 1) * 2.0 ** -46 * mag
+        xm = _mp(x)
+        hm.hm_cdd_sqr(x.ctypes.data_as(dp), out.ctypes.data_as(dp))
+        ref = xm * xm
+        assert abs(_mp(out) - ref) <= 2.0 ** -90 * abs(ref), x
+        w = _normalised_w(rng)
+        hm.hm_cdd_mul_d(x.ctypes.data_as(dp), w.real, w.imag, out.ctypes.data_as(dp))
+        ref = xm * mpmath.mpc(w.real, w.imag)
+        assert abs(_mp(out) - ref) <= 2.0 ** -90 * abs(ref), (x, w)
+        # renormalisation of a scaled copy: exact, high words normalised, low words below ulp/2
+        y = x * 2.0 ** int(rng.integers(-30, 9))
+        hm.hm_cdd_renorm(y.ctypes.data_as(dp), out.ctypes.data_as(dp), ctypes.byref(E))
+        assert _mp(out) * mpmath.mpf(2) ** E.value == _mp(y)
+        assert 0.5 <= max(abs(out[0]), abs(out[2])) < 1.0
+        assert abs(out[1]) <= 2.0 ** -53 * abs(out[0]) and abs(out[3]) <= 2.0 ** -53 * abs(out[2])
