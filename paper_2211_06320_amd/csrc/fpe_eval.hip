@@ -642,6 +642,13 @@ __device__ __forceinline__ int2 wave_start(const GroupCost &gc, int g, long long
 // fixed-point words per lane and window-wavefront slot: the sums of Q, then of Q'
 constexpr int kSlotWords = 8;
 
+// slot s of the window wavefronts (two per wavefront), stored by word pair:
+// pair q (words 2q and 2q + 1) of the 64 lanes lies at [q 64, q 64 + 64), so
+// a wavefront writes and reads each pair as one contiguous 1 KB run
+__device__ __forceinline__ longlong2 *slot_pairs(const EvalWs &W, size_t s) {
+    return reinterpret_cast<longlong2 *>(W.slots + s * kWave * kSlotWords);
+}
+
 // Split groups whose windows span more than kFinalShort + 1 window wavefronts
 // are long groups: the finalize kernel cuts their owners into pieces of
 // kLongPiece and spreads the pieces over its grid.  Owner ranges of two groups
@@ -1074,8 +1081,8 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
     // lie inside a split group's owner range, where the finalize kernel reads
     // its slot 0; every other slot that kernel reads is written below
     if (g == ge && c == ce) {
-        long long *s0 = W.slots + ((size_t)(2 * w) * kWave + lane) * kSlotWords;
-        for (int k = 0; k < kAccWords; ++k) s0[k] = 0;
+        longlong2 *s0 = slot_pairs(W, 2 * (size_t)w);
+        for (int q = 0; q < kAccWords / 2; ++q) s0[q * kWave + lane] = make_longlong2(0, 0);
     }
     // one pass per group segment: the consecutive tiles of one group this
     // wavefront owns
@@ -1220,11 +1227,16 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                     ed_out[j] = e;
                 }
             } else {
-                long long *slot = W.slots + ((size_t)(2 * w) * kWave + lane) * kSlotWords;
-                if (seg_c0 != clo)
-                    for (int k = 0; k < kAccWords; ++k) slot[k] = s_acc[k][t];
-                if (c != chi)
-                    for (int k = 0; k < kAccWords; ++k) slot[kWave * kSlotWords + k] = s_acc[k][t];
+                if (seg_c0 != clo) {
+                    longlong2 *sl = slot_pairs(W, 2 * (size_t)w);
+                    for (int q = 0; q < kAccWords / 2; ++q)
+                        sl[q * kWave + lane] = make_longlong2(s_acc[2 * q][t], s_acc[2 * q + 1][t]);
+                }
+                if (c != chi) {
+                    longlong2 *sl = slot_pairs(W, 2 * (size_t)w + 1);
+                    for (int q = 0; q < kAccWords / 2; ++q)
+                        sl[q * kWave + lane] = make_longlong2(s_acc[2 * q][t], s_acc[2 * q + 1][t]);
+                }
             }
         }
         if (c < chi) { ++c; }
@@ -1276,14 +1288,15 @@ __device__ __forceinline__ void final_out(const DevPlan &P, const EvalWs &W, int
 template <int kAccWords, int kU>
 __device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w0, int lane, long long *a) {
     longlong2 x[kU][kAccWords / 2];
+    const uint32_t loff = (uint32_t)lane * sizeof(longlong2);   // one lane offset for every slot
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-        const int w = w0 + u;                             // the same for the whole wavefront
+        const int w = __builtin_amdgcn_readfirstlane(w0 + u);   // the same for the whole wavefront
         if (w <= wy) {
-            const longlong2 *sl = reinterpret_cast<const longlong2 *>(
-                W.slots + ((size_t)(2 * w + (w == wx ? 1 : 0)) * kWave + lane) * kSlotWords);
+            const char *sb = reinterpret_cast<const char *>(slot_pairs(W, 2 * (size_t)w + (w == wx ? 1 : 0)));
 #pragma unroll
-            for (int k = 0; k < kAccWords / 2; ++k) x[u][k] = sl[k];
+            for (int k = 0; k < kAccWords / 2; ++k)
+                x[u][k] = *reinterpret_cast<const longlong2 *>(sb + loff + k * kWave * sizeof(longlong2));
         } else {
 #pragma unroll
             for (int k = 0; k < kAccWords / 2; ++k) x[u][k] = make_longlong2(0, 0);
@@ -1301,7 +1314,7 @@ __device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w
 __device__ __forceinline__ int long_pieces(int4 v) { return (v.z - v.y + kLongPiece) / kLongPiece; }
 
 template <bool D, bool B>
-__global__ __launch_bounds__(kFinalThreads, D ? 4 : 8) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
+__global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
                                                             long long *__restrict__ e_out,
                                                             double2 *__restrict__ md_out,
                                                             long long *__restrict__ ed_out, EvalWs W) {

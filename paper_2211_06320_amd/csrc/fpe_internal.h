@@ -71,7 +71,7 @@ struct EvalWs {
     int32_t *gblk_sum, *gblk_pre; // per k_groups workgroup: total work and (many groups) its scan
     int32_t *gseg_sum, *gseg_off; //   per 4096-entry segment of that scan
     int2 *wstart;                 // per window wavefront: first tile (group, chunk); n_waves + 1
-    long long *slots;             // per window wavefront, 2 x 64 lanes x 4: fixed-point partials
+    long long *slots;             // per window wavefront, 2 x kSlotWords x 64 lanes: fixed-point partials
     int32_t *ctl;                 // [0] total tile work, [5] points in the count table, [8] [9] split groups
     int64_t n, n_groups, n_sort_blocks, n_waves;
     int32_t cost_shift;           // tile work is counted in units of (16 << cost_shift) steps
