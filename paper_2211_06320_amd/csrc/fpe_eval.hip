@@ -208,8 +208,10 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, HP hk, HP hs,
     rc.z = zz;
     rc.l = l;
     rc.r = r;
-    rc.eref = er;
+    rc.j = j;
+    rc.pad = 0;
     W.rec[j] = rc;
+    W.eref[j] = er;
     return key;
 }
 
@@ -376,7 +378,6 @@ __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
     const int64_t idx = (int64_t)key * W.n_sort_blocks + j / kSortPoints;
     const int pos = W.tscan[idx] + s_boff[key / W.tab_ib] + rank;
     W.srec[pos] = W.rec[j];
-    W.sperm[pos] = j;
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
@@ -530,7 +531,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
         const int kr = s_kr[j];
         const size_t dst = (size_t)g0 * kWave + s_bin[kr / kBatchMaxPoints] + kr % kBatchMaxPoints;
         W.srec[dst] = W.rec[p0 + j];
-        W.sperm[dst] = (int)(p0 + j);
     }
     for (int q = m + t; q < ng * kWave; q += kBatchThreads) {
         const size_t dst = (size_t)g0 * kWave + q;
@@ -538,9 +538,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
         rc.z = make_double2(0.0, 0.0);
         rc.l = 1;
         rc.r = 0;
-        rc.eref = 0;
+        rc.j = -1;
+        rc.pad = 0;
         W.srec[dst] = rc;
-        W.sperm[dst] = -1;
     }
 }
 
@@ -1063,6 +1063,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
     __shared__ double s_ch[4][kWindowThreads];
     __shared__ long long s_che[2][kWindowThreads];
     __shared__ long long s_acc[kAccWords][kWindowThreads];   // fixed-point sums of the segment
+    __shared__ long long s_eref[kWindowThreads];              // eref of a lane whose window spans chunks
     if (w >= W.n_waves) return;
     const int nvalid = valid_points(W);
     const int G = (int)W.n_groups;
@@ -1099,9 +1100,10 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         const bool valid = idx < nvalid;
         PointRec rc;
         if (valid) rc = W.srec[idx];
-        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.eref = 0; }
+        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.j = -1; rc.pad = 0; }
         const int l = rc.l, r = rc.r;
         const bool multi = valid && (l / C != r / C);
+        if (multi) s_eref[threadIdx.x] = W.eref[rc.j];
         // z = w 2^ez with max(|Re w|, |Im w|) in [1/2, 1) (a stand-in for lanes
         // without a point); z itself is rebuilt exactly from w when needed
         const int ez = valid ? exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y))) : 0;
@@ -1184,7 +1186,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                         double2 m;
                         long long e;
                         normalise(qr, qi, E, m, e);
-                        const int j = W.sperm[idx];
+                        const int j = W.srec[idx].j;
                         m_out[j] = m;
                         e_out[j] = e;
                         if constexpr (D) {
@@ -1193,7 +1195,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                             ed_out[j] = e;
                         }
                     } else {
-                        const long long eref = W.srec[idx].eref;
+                        const long long eref = s_eref[t];
                         fix_add(S, qr, qi, E, eref, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t]);
                         if constexpr (D)
                             fix_add(S, dqr, dqi, E - ez, deriv_eref(eref, ez, r), s_acc[4][t], s_acc[5][t],
@@ -1216,9 +1218,9 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
             if (seg_c0 == clo && c == chi) {
                 double2 m;
                 long long e;
-                const long long eref = W.srec[idx].eref;
+                const long long eref = s_eref[t];
                 fix_out(S.fix_shift, S.fix_lo, s_acc[0][t], s_acc[1][t], s_acc[2][t], s_acc[3][t], eref, m, e);
-                const int j = W.sperm[idx];
+                const int j = W.srec[idx].j;
                 m_out[j] = m;
                 e_out[j] = e;
                 if constexpr (D) {
@@ -1261,7 +1263,7 @@ constexpr int kLongPer = kLongLds / kFinalThreads;   // long groups per thread i
 // the outputs of one point of a split group from its summed partials
 template <bool D, bool B>
 __device__ __forceinline__ void final_out(const DevPlan &P, const EvalWs &W, int g, const PointRec &rc,
-                                          int j, const long long *a, double2 *__restrict__ m_out,
+                                          int j, long long eref, const long long *a, double2 *__restrict__ m_out,
                                           long long *__restrict__ e_out, double2 *__restrict__ md_out,
                                           long long *__restrict__ ed_out) {
     double2 m;
@@ -1272,12 +1274,12 @@ __device__ __forceinline__ void final_out(const DevPlan &P, const EvalWs &W, int
         fs = Q.fix_shift;
         fl = Q.fix_lo;
     }
-    fix_out(fs, fl, a[0], a[1], a[2], a[3], rc.eref, m, e);
+    fix_out(fs, fl, a[0], a[1], a[2], a[3], eref, m, e);
     m_out[j] = m;
     e_out[j] = e;
     if constexpr (D) {
         const int ez = exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y)));
-        fix_out(fs, fl, a[4], a[5], a[6], a[7], deriv_eref(rc.eref, ez, rc.r), m, e);
+        fix_out(fs, fl, a[4], a[5], a[6], a[7], deriv_eref(eref, ez, rc.r), m, e);
         md_out[j] = m;
         ed_out[j] = e;
     }
@@ -1386,9 +1388,11 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
         const int p = g * kWave + lane;
         PointRec rc;
         int j = 0;
+        long long eref = 0;
         if (p < nvalid) {                              // requested with the slots
             rc = W.srec[p];
-            j = W.sperm[p];
+            j = rc.j;
+            if (j >= 0) eref = W.eref[j];
         }
         long long a[kAccWords] = {};
         for (int w0 = wa; w0 <= wb; w0 += 4) add_slots<kAccWords, 4>(W, wx, wb, w0, lane, a);
@@ -1412,7 +1416,7 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
             }
         }
         if (last && p < nvalid && rc.l / W.chunk != rc.r / W.chunk)
-            final_out<D, B>(P, W, g, rc, j, a, m_out, e_out, md_out, ed_out);
+            final_out<D, B>(P, W, g, rc, j, eref, a, m_out, e_out, md_out, ed_out);
     }
 }
 
@@ -1454,7 +1458,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
         const bool valid = idx < nvalid;
         PointRec rc;
         if (valid) rc = W.srec[idx];
-        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.eref = 0; }
+        else { rc.z = make_double2(0.0, 0.0); rc.l = 1; rc.r = 0; rc.j = -1; rc.pad = 0; }
         const int l = rc.l, r = rc.r;
         const int ez = valid ? exp_of(fmax(fabs(rc.z.x), fabs(rc.z.y))) : 0;
         const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
@@ -1462,7 +1466,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
         double gr = 0.0, gi = 0.0;
         int eg = 0;
         if (valid) {
-            const double2 gj = gin[W.sperm[idx]];
+            const double2 gj = gin[rc.j];
             const double gm = fmax(fabs(gj.x), fabs(gj.y));
             if (gm != 0.0 && isfinite(gm)) { eg = exp_of(gm); gr = ldexp(gj.x, -eg); gi = ldexp(gj.y, -eg); }
             else { gr = gj.x; gi = gj.y; }
@@ -1748,7 +1752,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.rec = (PointRec *)take(sizeof(PointRec) * n);
     w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
     w.srec = (PointRec *)take(sizeof(PointRec) * nslot);
-    w.sperm = (int32_t *)take(sizeof(int32_t) * nslot);
+    w.eref = (long long *)take(sizeof(long long) * (n > 0 ? n : 1));
     w.table = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.tscan = (int32_t *)take(sizeof(int32_t) * (tlen > 0 ? tlen : 1));
     w.bin_sum = (int32_t *)take(sizeof(int32_t) * (nseg_t > 0 ? nseg_t : 1));

@@ -44,12 +44,14 @@ struct DevPlan {
 };
 constexpr int32_t kNoFp32 = INT32_MIN;
 
-// What the window kernel needs of one point: z, its window [l, r] and the
-// reference exponent eref (every kept term is below 2^eref in magnitude).
+// What the window kernel needs of one point: z, its window [l, r] and its
+// input index j (-1 for a batch's padding).  The sort moves these 32 bytes; the
+// reference exponent eref (every kept term is below 2^eref in magnitude) stays
+// in input order, read only for windows that span several chunks.
 struct __align__(16) PointRec {
     double2 z;
     int32_t l, r;
-    long long eref;
+    int32_t j, pad;
 };
 
 // Workspace of one evaluation of n points, carved from the caller's buffer.
@@ -57,7 +59,7 @@ struct EvalWs {
     PointRec *rec;                // per point, input order (l > r: finished)
     int32_t *keyrank;             // per point, input order: lambda bin x (points per sort block) + rank
     PointRec *srec;               // records sorted by lambda bin
-    int32_t *sperm;               //   and their input indices
+    long long *eref;              // per point, input order: the reference exponent
     int32_t *table, *tscan;       // (sort block x bin) counts, and their bin-major scan
     int32_t *bin_sum, *bin_off;   // per table-scan segment (tab_ib bins)
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
