@@ -9,13 +9,13 @@
 //                N = max(Ehat + lambda Id) (eq. defN) by binary search over the
 //                cover vertices staged in LDS, the window [l, r] (eq. def:LRN) by
 //                two binary searches and a linear solve, the term count, a
-//                reference exponent and a lambda bin, written as one 32-byte
-//                record per point; per sort block of 2048 points, LDS counters
+//                reference exponent and a lambda bin (the window and the
+//                exponent written in input order); per sort block of 2048 points, LDS counters
 //                give each point its rank within its bin and the block's row of
 //                the (block x bin) count table
 //   k_scan_table exclusive scan of the count table in bin-major order
-//   k_scatter    counting-sort scatter of the records into lambda-bin order,
-//                one thread per point
+//   k_scatter    counting-sort scatter into lambda-bin order, one thread per
+//                point: a 32-byte record {z, window, input index} per point
 //   k_groups     per group of 64 consecutive sorted points (one wavefront):
 //                the union of their windows and the work of its C-term chunks
 //   k_scan_seg, k_partition   an equal-work partition of the (group, chunk)
@@ -204,15 +204,22 @@ __device__ __forceinline__ int bounds_point(const DevPlan &P, HP hk, HP hs,
     }
     if (terms) terms[j] = cnt;
     if (win) { win[2 * (size_t)j] = wl; win[2 * (size_t)j + 1] = wr; }
-    PointRec rc;
-    rc.z = zz;
-    rc.l = l;
-    rc.r = r;
-    rc.j = j;
-    rc.pad = 0;
-    W.rec[j] = rc;
+    W.lr[j] = make_int2(l, r);
     W.eref[j] = er;
     return key;
+}
+
+// the record the window kernel reads for point j, built where the sort moves
+// it: z from the caller's points, the window from k_bounds
+__device__ __forceinline__ PointRec point_rec(const double2 *__restrict__ z, const EvalWs &W, int j) {
+    PointRec rc;
+    rc.z = z[j];
+    const int2 lr = W.lr[j];
+    rc.l = lr.x;
+    rc.r = lr.y;
+    rc.j = j;
+    rc.pad = 0;
+    return rc;
 }
 
 // One sort block of kSortPoints consecutive points per workgroup: the points'
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_scan_table(EvalWs W) {
 // segment totals in LDS (at most kBins + 1 of them); workgroup 0 also stores
 // them, and their sum, for the later kernels.  Points of a bin that share a
 // sort block land in an unspecified order; results do not depend on it.
-__global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
+__global__ __launch_bounds__(1024) void k_scatter(int n, const double2 *__restrict__ z, EvalWs W) {
     __shared__ int32_t s_boff[kSeg];
     const int nseg = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
     {
@@ -377,7 +384,7 @@ __global__ __launch_bounds__(1024) void k_scatter(int n, EvalWs W) {
     if (key == kBins) return;                          // finished points are not sorted
     const int64_t idx = (int64_t)key * W.n_sort_blocks + j / kSortPoints;
     const int pos = W.tscan[idx] + s_boff[key / W.tab_ib] + rank;
-    W.srec[pos] = W.rec[j];
+    W.srec[pos] = point_rec(z, W, j);
 }
 
 // Work of the (group, chunk) tiles, in Horner steps, counted in units of
@@ -530,7 +537,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_bbounds(const DevPlan *__rest
     for (int j = t; j < m; j += kBatchThreads) {
         const int kr = s_kr[j];
         const size_t dst = (size_t)g0 * kWave + s_bin[kr / kBatchMaxPoints] + kr % kBatchMaxPoints;
-        W.srec[dst] = W.rec[p0 + j];
+        W.srec[dst] = point_rec(z, W, (int)(p0 + j));
     }
     for (int q = m + t; q < ng * kWave; q += kBatchThreads) {
         const size_t dst = (size_t)g0 * kWave + q;
@@ -1749,7 +1756,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     const int64_t nblk_g = (G + kGroupsPerBlock - 1) / kGroupsPerBlock;
     const int64_t nseg_t = (kBins + 1 + tab_ib - 1) / tab_ib, nseg_g = (nblk_g + kSeg - 1) / kSeg;
     EvalWs w;
-    w.rec = (PointRec *)take(sizeof(PointRec) * n);
+    w.lr = (int2 *)take(sizeof(int2) * (n > 0 ? n : 1));
     w.keyrank = (int32_t *)take(sizeof(int32_t) * n);
     w.srec = (PointRec *)take(sizeof(PointRec) * nslot);
     w.eref = (long long *)take(sizeof(long long) * (n > 0 ? n : 1));
@@ -1866,7 +1873,7 @@ static hipError_t launch_front(const DevPlan &P, const double2 *z, int ni, doubl
     if (P.nh > 0) {
         const int nseg_t = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
         k_scan_table<<<(unsigned)nseg_t, 1024, 0, stream>>>(W);
-        k_scatter<<<pb, 1024, 0, stream>>>(ni, W);
+        k_scatter<<<pb, 1024, 0, stream>>>(ni, z, W);
         launch_groups(P, W, nblk_g, stream);
     }
     return hipGetLastError();

@@ -56,7 +56,7 @@ struct __align__(16) PointRec {
 
 // Workspace of one evaluation of n points, carved from the caller's buffer.
 struct EvalWs {
-    PointRec *rec;                // per point, input order (l > r: finished)
+    int2 *lr;                     // per point, input order: its window [l, r] (l > r: finished)
     int32_t *keyrank;             // per point, input order: lambda bin x (points per sort block) + rank
     PointRec *srec;               // records sorted by lambda bin
     long long *eref;              // per point, input order: the reference exponent
