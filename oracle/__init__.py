@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
     L.ora_adjoint_coef.argtypes = [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64, ctypes.c_int64,
                                    _f64p, _i64p, _f64p, _i64p]
     L.ora_absum.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
+    L.ora_eval_fp64.argtypes = [ctypes.c_void_p, _f64p, ctypes.c_int64, _f64p, _i64p, ctypes.c_int]
+    L.ora_level_sets.argtypes = [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64, _f64p, _f64p, _f64p]
     L.ora_cancel_bound.argtypes = [ctypes.c_void_p, _f64p, _f64p, _f64p, _i64p, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int32)]
     _LIB = L
@@ -169,6 +171,30 @@ class OraclePlan:
                        nthreads or default_threads())
         return {"m": m.view(np.complex128), "e": e, "l": l, "r": r, "terms": t,
                 "dwin_m": dm, "dwin_e": de, "lambda": lam, "N": N}
+
+    def eval_fp64(self, z, nthreads: int | None = None):
+        """Q_lambda(z) with the window sum in plain FP64 (z^l by binary powering,
+        Horner's rule over the window): (m, e) with Q = m 2^e."""
+        zri = _as_ri(np.atleast_1d(z))
+        n = zri.shape[0] // 2
+        m = np.zeros(2 * n, np.float64)
+        e = np.zeros(n, np.int64)
+        lib().ora_eval_fp64(self._h, _ptr(zri, _f64p), n, _ptr(m, _f64p), _ptr(e, _i64p),
+                            nthreads or default_threads())
+        return m.view(np.complex128), e
+
+    def level_sets(self, lam, dlevel=None):
+        """N, x_L, x_R of eq. (def:LRN) at the given values of lambda (as eval
+        computes them for a point with that lambda), the level moved to
+        N - T + dlevel when dlevel is given."""
+        lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
+        n = lam.shape[0]
+        dl = None if dlevel is None else np.ascontiguousarray(np.broadcast_to(dlevel, (n,)), np.float64)
+        N = np.zeros(n, np.float64)
+        xl = np.zeros(n, np.float64)
+        xr = np.zeros(n, np.float64)
+        lib().ora_level_sets(self._h, _ptr(lam, _f64p), None if dl is None else _ptr(dl, _f64p), n, _ptr(N, _f64p), _ptr(xl, _f64p), _ptr(xr, _f64p))
+        return N, xl, xr
 
     def cancel_bound(self, z, N, m, e) -> np.ndarray:
         """Upper bound of the cancelled bits c of eq. (def_prec_loss) per point,

@@ -18,6 +18,9 @@
  *                     [l, r], and Q_lambda(z) = sum over G_p in [l, r]  (reducedQlambda)
  *   ora_horner        P(z) = sum_k a_k z^k by compensated Horner        Section 4.1 (the plain definition);
  *                     (error-free transforms), unbounded exponent       compensated Horner is cited in Section 1
+ *   ora_eval_fp64     the same Q_lambda(z), window sum in plain FP64     Algorithm A_p at p = 53 (CPU timing)
+ *                     (z^l by binary powering, Horner over the window)   Section 5.2
+ *   ora_level_sets    N, x_L, x_R of eq. (def:LRN) for given lambdas     eqs. (defN), (def:LRN)
  *   ora_absum         D(z) = sum_k |a_k| |z|^k                          tolerance scale of the parity metric
  *   ora_eval_deriv    Q'_lambda(z) = sum over the same kept terms of    derivative of eq. (reducedQlambda);
  *                     k a_k z^(k-1)                                      Newton's method, Section 7.2
@@ -393,6 +396,59 @@ static double ora_log2abs(double x, double y)
 /* ------------------------------------------------------------------------- */
 /* Evaluation of one point (Algorithm A_p, second block; Section 5.2).        */
 /* ------------------------------------------------------------------------- */
+/* evaluation for one lambda: k_lambda = argmax(Ehat + lambda Id), N (eq. defN)
+   and the real ends x_L <= x_R of the level set {x : Ehat(x) + lambda x >= N - T}
+   (eq. def:LRN); returns N.  P must have at least one cover vertex.  dlev
+   moves the level to N - T + dlev (0 in the method; tests move it by the size
+   of its rounding). */
+static double ora_level_set(const ora_plan *P, double lam, double dlev, double *xLo, double *xRo)
+{
+    /* k_lambda = argmax(Ehat + lambda Id); the maximum of a concave
+       piecewise-linear function is at a vertex; scan them all, keep the
+       leftmost maximiser. */
+    int64_t nh = P->nh, istar = 0;
+    double *F = malloc(sizeof(double) * (size_t)nh);
+    for (int64_t i = 0; i < nh; ++i) {
+        F[i] = (double)P->hs[i] + lam * (double)P->hk[i];
+        if (F[i] > F[istar]) istar = i;
+    }
+    /* N = Ehat(k_lambda) + lambda k_lambda (eq. defN) */
+    double N = F[istar];
+    /* the window at the level N - p - s(d) - 3 (eq. def:LRN); the level set of
+       the concave function is an interval [x_L, x_R]. */
+    double L = N - (double)P->T + dlev;
+    double xL, xR;
+    if (F[0] >= L) xL = (double)P->hk[0];
+    else {
+        int64_t i = istar;
+        while (F[i - 1] >= L) --i;      /* F[i-1] < L <= F[i] */
+        xL = (double)P->hk[i - 1] + (L - F[i - 1]) * (double)(P->hk[i] - P->hk[i - 1]) / (F[i] - F[i - 1]);
+    }
+    if (F[nh - 1] >= L) xR = (double)P->hk[nh - 1];
+    else {
+        int64_t i = istar;
+        while (F[i + 1] >= L) ++i;      /* F[i] >= L > F[i+1] */
+        xR = (double)P->hk[i] + (F[i] - L) * (double)(P->hk[i + 1] - P->hk[i]) / (F[i] - F[i + 1]);
+    }
+    free(F);
+    *xLo = xL;
+    *xRo = xR;
+    return N;
+}
+
+/* N, x_L and x_R (as ora_level_set) for n given values of lambda and level
+   offsets dlev (NULL: 0); NaN for a plan with no vertex.  Tests use it to find
+   the points whose window ends would move under perturbations of lambda and
+   of the level of the size of their rounding. */
+void ora_level_sets(const ora_plan *P, const double *lam, const double *dlev, int64_t n, double *N, double *xL,
+                    double *xR)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        if (P->nh == 0 || !isfinite(lam[j])) { N[j] = xL[j] = xR[j] = NAN; continue; }
+        N[j] = ora_level_set(P, lam[j], dlev ? dlev[j] : 0.0, xL + j, xR + j);
+    }
+}
+
 typedef struct {
     double m[2]; int64_t e;     /* Q_lambda(z) = (m0 + i m1) 2^e */
     double md[2]; int64_t de;   /* Q'_lambda(z) = sum over the kept terms of k a_k z^(k-1) */
@@ -427,35 +483,11 @@ static void ora_eval1(const ora_plan *P, double zr, double zi, int deriv, ora_re
     /* evaluation: lambda = log2|z| (eq. defLambda) */
     double lam = ora_log2abs(zr, zi);
     o->lambda = lam;
-    /* evaluation: k_lambda = argmax(Ehat + lambda Id); the maximum of a concave
-       piecewise-linear function is at a vertex; scan them all, keep the
-       leftmost maximiser. */
-    int64_t nh = P->nh, istar = 0;
-    double *F = malloc(sizeof(double) * (size_t)nh);
-    for (int64_t i = 0; i < nh; ++i) {
-        F[i] = (double)P->hs[i] + lam * (double)P->hk[i];
-        if (F[i] > F[istar]) istar = i;
-    }
-    /* evaluation: N = Ehat(k_lambda) + lambda k_lambda (eq. defN) */
-    double N = F[istar];
-    o->N = N;
-    /* evaluation: the window [l, r] at the level N - p - s(d) - 3 (eq. def:LRN);
-       the level set of the concave function is an interval [x_L, x_R]. */
-    double L = N - (double)P->T;
+    /* evaluation: k_lambda, N (eq. defN) and the level set [x_L, x_R] of
+       eq. (def:LRN) */
     double xL, xR;
-    if (F[0] >= L) xL = (double)P->hk[0];
-    else {
-        int64_t i = istar;
-        while (F[i - 1] >= L) --i;      /* F[i-1] < L <= F[i] */
-        xL = (double)P->hk[i - 1] + (L - F[i - 1]) * (double)(P->hk[i] - P->hk[i - 1]) / (F[i] - F[i - 1]);
-    }
-    if (F[nh - 1] >= L) xR = (double)P->hk[nh - 1];
-    else {
-        int64_t i = istar;
-        while (F[i + 1] >= L) ++i;      /* F[i] >= L > F[i+1] */
-        xR = (double)P->hk[i] + (F[i] - L) * (double)(P->hk[i + 1] - P->hk[i]) / (F[i] - F[i + 1]);
-    }
-    free(F);
+    double N = ora_level_set(P, lam, 0.0, &xL, &xR);
+    o->N = N;
     int64_t l = (int64_t)ceil(xL - ORA_ETA), r = (int64_t)floor(xR + ORA_ETA);
     if (l < P->v) l = P->v;
     if (r > P->dt) r = P->dt;
@@ -613,10 +645,83 @@ static void ora_absum1(const double *a, int64_t d, double zr, double zi, double 
 }
 
 /* ------------------------------------------------------------------------- */
+/* The evaluation with its window sum in plain FP64 (Algorithm A_p, second    */
+/* block, at the precision of the method's target): lambda, N and [l, r] as   */
+/* in ora_eval1, z^l by binary powering (Section 5.2) with a separate binary  */
+/* exponent, then Horner's rule over the window with the terms outside G_p    */
+/* skipped, on the coefficients scaled by 2^-c, c = floor(N - lambda l), so   */
+/* that every kept term a_k z^(k-l) 2^-c is below 4 in modulus (eq. shear).   */
+/* The CPU baseline times this form; its values are pinned against exact      */
+/* rationals.  The Horner partials stay in the FP64 range while |lambda| W    */
+/* and the spread of the cover over the window stay below about 900 bits.     */
+/* ------------------------------------------------------------------------- */
+static void ora_cmul_norm(double *xr, double *xi, int64_t *xe, double yr, double yi, int64_t ye)
+{
+    double r = *xr * yr - *xi * yi, i = *xr * yi + *xi * yr;
+    double mx = fmax(fabs(r), fabs(i));
+    int k = 0;
+    if (mx != 0.0) frexp(mx, &k);
+    *xr = ldexp(r, -k);
+    *xi = ldexp(i, -k);
+    *xe += ye + k;
+}
+
+static void ora_eval1_fp64(const ora_plan *P, double zr, double zi, double *m, int64_t *e)
+{
+    m[0] = m[1] = 0.0;
+    *e = 0;
+    if (!isfinite(zr) || !isfinite(zi)) { m[0] = m[1] = NAN; return; }
+    if (P->nh == 0) return;                          /* P == 0 */
+    const double *a = P->coef;
+    if (zr == 0.0 && zi == 0.0) {                    /* P(0) = a_0 */
+        if (P->v == 0) xc_out(xc_from(a[0], a[1]), m, e);
+        return;
+    }
+    double lam = ora_log2abs(zr, zi);
+    double xL, xR;
+    double N = ora_level_set(P, lam, 0.0, &xL, &xR);
+    int64_t l = (int64_t)ceil(xL - ORA_ETA), r = (int64_t)floor(xR + ORA_ETA);
+    if (l < P->v) l = P->v;
+    if (r > P->dt) r = P->dt;
+    /* z^l = (pr + i pi) 2^pe by right-to-left binary powering of w = z 2^-ez */
+    int ez = max_exp(zr, zi);
+    double wr = ldexp(zr, -ez), wi = ldexp(zi, -ez);
+    double pr = 1.0, pi = 0.0, br = wr, bi = wi;
+    int64_t pe = 0, be = 0;
+    for (int64_t n = l; n > 0; n >>= 1) {
+        if (n & 1) ora_cmul_norm(&pr, &pi, &pe, br, bi, be);
+        if (n > 1) ora_cmul_norm(&br, &bi, &be, br, bi, be);
+    }
+    pe += l * (int64_t)ez;
+    /* Horner's rule over the window on a_k 2^-c */
+    int64_t c = (int64_t)floor(N - lam * (double)l);
+    int exact_scale = c > -1000 && c < 1000;
+    double sc = exact_scale ? ldexp(1.0, (int)-c) : 0.0;
+    double hr = 0.0, hi = 0.0;
+    for (int64_t k = r; k >= l; --k) {
+        double tr = hr * zr - hi * zi, ti = hr * zi + hi * zr;
+        if (P->good[k]) {
+            if (exact_scale) { tr += a[2 * k] * sc; ti += a[2 * k + 1] * sc; }
+            else { tr += ldexp(a[2 * k], (int)-c); ti += ldexp(a[2 * k + 1], (int)-c); }
+        }
+        hr = tr;
+        hi = ti;
+    }
+    double qr = hr * pr - hi * pi, qi = hr * pi + hi * pr;
+    double mx = fmax(fabs(qr), fabs(qi));
+    if (mx == 0.0) return;
+    int k;
+    frexp(mx, &k);
+    m[0] = ldexp(qr, -k);
+    m[1] = ldexp(qi, -k);
+    *e = pe + c + k;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Batch drivers (points are independent; threads split the point range).    */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    int kind;                  /* 0 = eval, 1 = horner, 2 = absum */
+    int kind;                  /* 0 = eval, 1 = horner, 2 = absum, 3 = eval, FP64 window sum */
     const ora_plan *P;
     const double *coef; int64_t d;
     const double *z; int64_t i0, i1;
@@ -647,6 +752,8 @@ static void *ora_worker(void *arg)
             if (J->N) J->N[i] = o.N;
         } else if (J->kind == 1) {
             ora_horner1(J->coef, J->d, zr, zi, J->m + 2 * i, J->e + i);
+        } else if (J->kind == 3) {
+            ora_eval1_fp64(J->P, zr, zi, J->m + 2 * i, J->e + i);
         } else {
             ora_absum1(J->coef, J->d, zr, zi, J->m + i, J->e + i);
         }
@@ -690,6 +797,13 @@ void ora_eval_deriv(const ora_plan *P, const double *z, int64_t n, double *m, in
                     int nthreads)
 {
     ora_job J = { 0, P, NULL, 0, z, 0, 0, m, e, NULL, NULL, NULL, dwin_m, dwin_e, NULL, NULL, md, de, ddm, dde };
+    ora_run(J, n, nthreads);
+}
+
+/* Q_lambda(z) with the window sum in plain FP64 (ora_eval1_fp64) */
+void ora_eval_fp64(const ora_plan *P, const double *z, int64_t n, double *m, int64_t *e, int nthreads)
+{
+    ora_job J = { 3, P, NULL, 0, z, 0, 0, m, e, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL };
     ora_run(J, n, nthreads);
 }
 
