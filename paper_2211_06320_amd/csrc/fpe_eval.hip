@@ -1438,6 +1438,8 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
 // is emitted; the 64 lanes' terms of four consecutive k at a time are summed
 // across the wavefront by a reduce-scatter and added to grad_a[k] (FP64
 // atomics: the order of the additions, hence the last bits, can vary).
+constexpr int kRenormSteps = 256;   // products by conj(w) between two folds of the term mantissa
+
 __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const double2 *__restrict__ gin,
                                                             double2 *__restrict__ grad_a, EvalWs W) {
     const int lane = threadIdx.x % kWave;
@@ -1490,10 +1492,12 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                 double pr, pi;
                 long long pe;
                 tile_power(pw, l, lo, act, c, C, wr, wi, s_ch, s_che, t, pr, pi, pe);
-                // term k = (tr + i ti) 2^E: the mantissa g conj(w^k) (|w| in [1/2, 2^(1/2)),
-                // so over one chunk it stays within [2^-514, 2^258]) and the exponent
-                // eg + pe + k ez apart; only the emitted term is scaled (and may
-                // saturate or flush)
+                // term k = (tr + i ti) 2^E: the mantissa g conj(w^k) and the
+                // exponent eg + pe + k ez apart; only the emitted term is scaled
+                // (and may saturate or flush).  |w| lies in [1/2, 2^(1/2)), so
+                // the mantissa is folded into E every kRenormSteps products
+                // (within [2^-258, 2^129] of its start between two folds, for
+                // any chunk length)
                 double tr = fma(gr, pr, gi * pi);
                 double ti = fma(gi, pr, -gr * pi);
                 long long E = (long long)eg + pe + (long long)lo * ez;
@@ -1502,6 +1506,16 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                 // 16 q .. 16 q + 15 with index q; xor 8, 4, 2, 1 sum those)
                 const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
                 for (int k0 = Klo; k0 <= Khi; k0 += 4) {
+                    if (((k0 - Klo) & (kRenormSteps - 1)) == 0 && k0 != Klo) {
+                        // exact: a power of two moves from the mantissa to E
+                        const double mx = fmax(fabs(tr), fabs(ti));
+                        if (mx != 0.0 && isfinite(mx)) {
+                            const int ex = exp_of(mx);
+                            tr = ldexp(tr, -ex);
+                            ti = ldexp(ti, -ex);
+                            E += ex;
+                        }
+                    }
                     double vr[4], vi[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {

@@ -26,8 +26,8 @@ U = 2.0 ** -53
 CHUNK = 512
 
 
-def tol_grad_a(w_partials: int) -> float:
-    return U * (2 * CHUNK + 40 + w_partials)
+def tol_grad_a(w_partials: int, chunk: int = CHUNK) -> float:
+    return U * (2 * chunk + 40 + w_partials)
 
 
 @pytest.fixture(scope="module")
@@ -68,8 +68,9 @@ def xval(m, e):
         return np.ldexp(np.asarray(m).real, e) + 1j * np.ldexp(np.asarray(m).imag, e)
 
 
-def check(fpe, c, z, g, label, w_partials=None):
+def check(fpe, c, z, g, label, w_partials=None, chunk=CHUNK):
     plan = fpe.precondition(to_dev(c), 53)
+    plan.set_chunk(chunk)
     ga, gz = plan.adjoint(to_dev(z), to_dev(g))
     torch.cuda.synchronize()
     ga, gz = ga.cpu().numpy(), gz.cpu().numpy()
@@ -82,7 +83,7 @@ def check(fpe, c, z, g, label, w_partials=None):
     err = np.abs(ga[ok] - want[ok]) / S[ok]
     if w_partials is None:
         w_partials = math.ceil(len(z) / 64)
-    tol = tol_grad_a(w_partials)
+    tol = tol_grad_a(w_partials, chunk)
     worst = float(err.max(initial=0.0))
     say(f"  {label}: grad_a max scaled error {worst:.3e} (tol {tol:.3e}) on {ok.sum()} coefficients")
     assert worst <= tol, (worst, math.log2(max(worst, 1e-300)))
@@ -109,6 +110,23 @@ def test_adjoint_small(fpe):
     g = scaled_g(wl.coeffs, z, 62)
     g[-5:] = [1 + 2j, 1, 0, 0.5, 0.25j]
     check(fpe, wl.coeffs, z, g, "uniform d=1000")
+
+
+@pytest.mark.parametrize("chunk", [1024, 2048])
+def test_adjoint_chunk_lengths_w_half(fpe, chunk):
+    """Long chunks on points with max(|Re z|, |Im z|) just above 1, where the
+    unit-scale mantissa w = z / 2 has |w| near 1/2: over a chunk of 2048 the
+    term mantissa g conj(w)^k would fall by 2^-2048 without its folds into
+    the exponent; for |z| > 1 those are the largest terms of grad_a."""
+    d = 20_000
+    c = workloads.uniform_coeffs(d, 23)
+    rng = np.random.default_rng(67)
+    th = rng.uniform(-0.05, 0.05, 2000) + rng.integers(0, 4, 2000) * (np.pi / 2)
+    z = 2.0 ** rng.uniform(0.002, 0.004, 2000) * np.exp(1j * th)
+    z = z[np.maximum(np.abs(z.real), np.abs(z.imag)) >= 1.0]
+    r = oracle.precondition(c, 53).eval(z)
+    assert ((r["r"] - r["l"]) >= chunk).sum() > 100
+    check(fpe, c, z, scaled_g(c, z, 68), f"|z| just above 1, chunk {chunk}", chunk=chunk)
 
 
 def test_adjoint_long_windows(fpe):
