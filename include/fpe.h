@@ -170,6 +170,28 @@ fpe_status fpe_eval(fpe_plan_t plan, const double *z_dev, int64_t n,
                     double *m_dev, int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
                     void *workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
+/* fpe_eval without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results as fpe_eval, bit for bit, with the workspace in a static device array
+ * of 96 MiB that the library holds on each device it runs on until the process
+ * ends.  The call makes no hipMalloc, hipFree or other allocating call; the
+ * first call on a device looks up the array's address there
+ * (hipGetSymbolAddress).
+ *
+ *   plan, z_dev, n, m_dev, e_dev, terms_dev, window_dev, stream: as fpe_eval.
+ *
+ * Limit: the evaluation's workspace (fpe_eval's layout, sized for this call
+ * alone) must fit in the 96 MiB array; 2^17 points always fit, and larger n
+ * fails with FPE_ERR_WORKSPACE (use fpe_eval then).  Every call on one device
+ * shares that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (two streams, two threads) race and must be
+ * serialised by the caller.  Errors: those of fpe_eval, with
+ * FPE_ERR_WORKSPACE meaning "n above the static scratch's limit". */
+fpe_status fpe_eval_noalloc(fpe_plan_t plan, const double *z_dev, int64_t n,
+                            double *m_dev, int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
+                            hipStream_t stream);
+
 /* Q_lambda(z_j) as fpe_eval does, and in the same pass its derivative
  * Q'_lambda(z_j) = sum over k in G_p within [l_j, r_j] of k a_k z_j^(k-1): the
  * derivative of the terms the method keeps, through the same window (the

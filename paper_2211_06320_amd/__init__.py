@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_workspace_size.argtypes = [vp, i64, P(sz)]
     L.fpe_eval.restype = i32
     L.fpe_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_eval_noalloc.restype = i32
+    L.fpe_eval_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     L.fpe_eval_deriv.restype = i32
     L.fpe_eval_deriv.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_newton_step.restype = i32
@@ -241,6 +243,17 @@ class Plan:
             return m, e, t, w
         return m, e
 
+
+    def eval_noalloc(self, z, out, terms=None, window=None, stream=None):
+        """fpe_eval_noalloc: Q_lambda(z) into the caller's tensors out = (m, e)
+        (and terms / window when given), with the library's static device
+        scratch as workspace; allocates nothing."""
+        z = _dev_complex(z, "z")
+        m, e = out
+        _check(lib().fpe_eval_noalloc(self._h, z.data_ptr(), z.shape[0], m.data_ptr(), e.data_ptr(),
+                                      terms.data_ptr() if terms is not None else None,
+                                      window.data_ptr() if window is not None else None, _stream(stream)))
+        return m, e
 
     def set_chunk(self, chunk: int) -> None:
         """Chunk length of the tiles for later evaluations (0: automatic)."""

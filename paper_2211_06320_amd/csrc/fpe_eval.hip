@@ -1756,7 +1756,7 @@ int cost_shift_for_chunks(int64_t G, int64_t chunks, int chunk) {
 }
 
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind, int64_t batch_groups,
-                            int chunk) {
+                            int chunk, bool tight) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) { char *p = b ? b + off : nullptr; off = align_up(off + bytes); return p; };
@@ -1789,14 +1789,15 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
     w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
-    // one workspace serves every tile kernel
-    const int64_t nw_max = std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
-                                    std::max(window_waves(kTileAdjoint), window_waves(kTileBatch)));
     // as many window wavefronts as are resident, but no more than four per
     // group: a small evaluation then spreads its few tiles over few wavefronts
     w.n_waves = std::min<int64_t>(window_waves(kind), std::max<int64_t>(4 * G, 1));
     // the finalize kernel holds the long groups in LDS
     w.n_waves = std::min<int64_t>(w.n_waves, (int64_t)(kLongLds - 1) * kFinalShort);
+    // one workspace serves every tile kernel, unless sized for this kind alone
+    const int64_t nw_max = tight ? w.n_waves
+                                 : std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
+                                            std::max(window_waves(kTileAdjoint), window_waves(kTileBatch)));
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     const int64_t nlong = long_cap(nw_max);
@@ -1893,14 +1894,20 @@ static hipError_t launch_front(const DevPlan &P, const double2 *z, int ni, doubl
     return hipGetLastError();
 }
 
+// tight: the workspace is laid out for this evaluation alone (the layout the
+// no-allocation entry point uses); otherwise as fpe_eval_workspace_size says.
+// With tight, no profiling events are recorded (creating one may allocate).
 static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
                             double *md_dev, int64_t *ed_dev, int32_t *terms_dev, int64_t *window_dev,
-                            void *workspace_dev, size_t workspace_bytes, hipStream_t stream) {
+                            void *workspace_dev, size_t workspace_bytes, hipStream_t stream, bool tight = false) {
     const bool deriv = md_dev != nullptr;
     if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
     size_t need = 0;
     fpe_status st = fpe_eval_workspace_size(plan, n, &need);
     if (st != FPE_OK) return st;
+    if (tight)
+        need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, deriv ? kTileDeriv : kTileValue, -1,
+                                    plan_chunk(plan, n), true);
     if (n == 0) { set_error(""); return FPE_OK; }
     if (!z_dev || !m_dev || !e_dev || !workspace_dev || (deriv && !ed_dev))
         return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
@@ -1910,7 +1917,9 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
         reinterpret_cast<uintptr_t>(m_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue, -1, plan_chunk(plan, n));
+    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue, -1, plan_chunk(plan, n),
+                         tight);
+    const bool prof = g_prof.on && !tight;
     const DevPlan &P = plan->dev;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
     double2 *m = reinterpret_cast<double2 *>(m_dev);
@@ -1925,14 +1934,14 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
     if (P.nh > 0) {
         const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (g_prof.on) {
+        if (prof) {
             FPE_HIP_CHECK(prof_event(&ev0));
             FPE_HIP_CHECK(prof_event(&ev1));
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
         if (deriv) k_window<true, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, md, ed, W);
         else k_window<false, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
-        if (g_prof.on) {
+        if (prof) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
         }
@@ -1960,6 +1969,63 @@ extern "C" fpe_status fpe_eval_deriv(fpe_plan_t plan, const double *z_dev, int64
     if (n > 0 && (!md_dev || !ed_dev)) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     return eval_impl(plan, z_dev, n, m_dev, e_dev, md_dev, ed_dev, nullptr, nullptr, workspace_dev,
                      workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------- no allocation
+// fpe_eval_noalloc: fpe_eval with its workspace in a static device array of
+// kScratchBytes instead of a caller buffer.  Each device the library runs on
+// holds its own copy of the array from the module's load to the end of the
+// process; its address on a device comes from hipGetSymbolAddress once, on the
+// first call with that device current (the name `scratch` in host code is a
+// host-side stand-in, never a device address).  The evaluation writes every
+// word of the workspace it later reads (k_bounds clears the counters,
+// k_partition the long groups' accumulators), so nothing needs clearing
+// between calls; calls that overlap on one device share the array and race.
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+fpe_status scratch_address(void **out) {
+    int dev = 0;
+    FPE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FPE_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+            return fail(FPE_ERR_HIP, "static scratch array has no aligned device address");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return FPE_OK;
+}
+}  // namespace
+
+extern "C" fpe_status fpe_eval_noalloc(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev,
+                                       int64_t *e_dev, int32_t *terms_dev, int64_t *window_dev,
+                                       hipStream_t stream) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (n < 0 || n >= INT32_MAX) return fail(FPE_ERR_INVALID_ARG, "n out of range");
+    if (n == 0) { set_error(""); return FPE_OK; }
+    FPE_HIP_CHECK(device_setup());
+    if (cost_shift_for(plan->dev, n, kChunkMin) < 0)
+        return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
+    const size_t need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, kTileValue, -1, plan_chunk(plan, n), true);
+    if (need > kScratchBytes)
+        return fail(FPE_ERR_WORKSPACE, "fpe_eval_noalloc: " + std::to_string(n) + " points need " +
+                                           std::to_string(need) + " bytes of workspace, above the static " +
+                                           std::to_string(kScratchBytes) + "-byte scratch (use fpe_eval)");
+    void *ws = nullptr;
+    fpe_status st = scratch_address(&ws);
+    if (st != FPE_OK) return st;
+    return eval_impl(plan, z_dev, n, m_dev, e_dev, nullptr, nullptr, terms_dev, window_dev, ws, kScratchBytes,
+                     stream, true);
 }
 
 extern "C" fpe_status fpe_profile_enable(int32_t on) {

@@ -87,8 +87,10 @@ struct EvalWs {
     int32_t chunk;                // coefficient chunk length C of the tiles (a power of two)
 };
 
+// tight: the per-wavefront tables sized for this kind of tile kernel alone (by
+// default one workspace serves every tile kernel)
 size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base, int kind,
-                            int64_t batch_groups = -1, int chunk = kChunk);
+                            int64_t batch_groups = -1, int chunk = kChunk, bool tight = false);
 
 // Read-only tables are read through the constant address space in device code:
 // a wave-uniform index then becomes a scalar load, one per wavefront, broadcast
