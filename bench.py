@@ -15,8 +15,9 @@ Besides the JSON fields the driver reads, the line carries:
                 the HBM bytes per launch recorded with rocprofv3 counters in
                 profiles/k_window_uniform_d1e6_traffic.txt, reported only while
                 the window kernel's sources are the ones those counters measured
-  cpu_baseline  the oracle (plain C, FP64 plan + double-double window sum) on a
-                bounded sample of the same points, on the host's cores
+  cpu_baseline  the oracle (plain C) with its plain-FP64 window sum over every
+                point, on the host's threads (at most 16) and on one thread;
+                its double-double mode on a sample beside it
   horner_gpu    the same-GPU Horner baseline over all points
   max_scaled_err  max |FPE - reference| / sum|a_k||z|^k on a seeded sample,
                 the reference being the oracle's window sum at p = 116
@@ -246,7 +247,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-polynomial leg")
     ap.add_argument("--chunk", type=int, default=0,
                     help="chunk length of the tiles (0: autotuned before the timed steps)")
-    ap.add_argument("--cpu-sample", type=int, default=131072)
+    ap.add_argument("--cpu-sample", type=int, default=131072,
+                    help="points of the double-double oracle timing")
     ap.add_argument("--check-sample", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a kernel of known traffic, "
@@ -307,25 +309,31 @@ def main() -> int:
         log(f"copy calibration: {nb} bytes device to device")
         del src, dst
     fpe.profile_read()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # an event between consecutive steps: the K step durations (for the median)
+    # and their sum (the mean), from the same records
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record()
+    evs[0].record()
     for i in range(args.steps):
         # the window kernel is timed with an event pair on every PROFILE_EVERY-th
         # step: each pair adds a few microseconds of stream serialisation
         fpe.profile_enable(i % PROFILE_EVERY == 0)
         plan.eval(z, out=out)
-    ev1.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     fpe.profile_enable(False)
-    total_ms = ev0.elapsed_time(ev1)
+    total_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] +
+                                                                             step_ms[len(step_ms) // 2])
     win_ms, launches = fpe.profile_read()
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step * 1e-3)
     win_avg_ms = win_ms / max(launches, 1)
     achieved = flops / (win_avg_ms * 1e-3) / 1e12
     traffic = recorded_traffic(wl.name, chunk)
-    log(f"eval {ms_per_step:.3f} ms/step ({value:.3e} evals/s); window kernel {win_avg_ms:.3f} ms, "
+    log(f"eval {ms_per_step:.3f} ms/step mean, {median_ms:.3f} median ({value:.3e} evals/s); "
+        f"window kernel {win_avg_ms:.3f} ms, "
         f"{achieved:.2f} TFLOP/s algorithmic")
 
     res = {
@@ -336,6 +344,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": median_ms,
+        "value_median": n / (median_ms * 1e-3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -388,16 +398,30 @@ def main() -> int:
         res["batched"] = batched_leg(fpe, workloads, oracle, np, torch, dev, args.steps)
 
     if not args.no_cpu:
+        # the oracle's plain-FP64 window sum (its plan in FP64, z^l by binary
+        # powering, Horner's rule over the window) over every point, on the
+        # host's threads (at most 16, the GPU machine's CPU share) and on one
+        # thread; its double-double mode (the parity reference) on a sample
         threads = oracle.default_threads()
-        zs = wl.points[:args.cpu_sample]
         cplan = oracle.precondition(wl.coeffs, wl.p_bits)
         t0 = time.perf_counter()
-        cplan.eval(zs, nthreads=threads)
+        cplan.eval_fp64(wl.points, nthreads=threads)
         dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": len(zs) / dt, "unit": "evaluations/s", "cores": threads, "kind": "oracle",
-                               "sample": f"first {len(zs)} of the {n} points of {wl.name}, p={wl.p_bits}: "
-                                         f"FP64 plan + double-double window sum, {threads} threads, {dt:.2f} s wall"}
-        log(f"cpu oracle {len(zs) / dt:.3e} evals/s on {threads} threads")
+        t0 = time.perf_counter()
+        cplan.eval_fp64(wl.points, nthreads=1)
+        dt1 = time.perf_counter() - t0
+        zs = wl.points[:args.cpu_sample]
+        t0 = time.perf_counter()
+        cplan.eval(zs, nthreads=threads)
+        dtd = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n / dt, "unit": "evaluations/s", "cores": threads, "kind": "oracle",
+                               "sample": f"all {n} points of {wl.name}, p={wl.p_bits}: the oracle's plain-FP64 "
+                                         f"window sum, {threads} threads, {dt:.2f} s wall",
+                               "single_thread": {"value": n / dt1, "cores": 1, "seconds": dt1},
+                               "double_double": {"value": len(zs) / dtd, "cores": threads, "points": len(zs),
+                                                 "seconds": dtd}}
+        log(f"cpu oracle (plain FP64) {n / dt:.3e} evals/s on {threads} threads, {n / dt1:.3e} on 1 thread; "
+            f"double-double {len(zs) / dtd:.3e} evals/s on {threads} threads")
 
     print(json.dumps(res), flush=True)
     return 0
