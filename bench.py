@@ -159,6 +159,100 @@ def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> 
     return out
 
 
+def sparse_gap_digits(good, terms, window, np) -> float:
+    """Sum over the points of the binary digits of the gaps between consecutive
+    kept indices (a product by a power z^(2^j) per digit in the sparse form)."""
+    g = np.flatnonzero(good)
+    if g.size < 2:
+        return 0.0
+    cp = np.concatenate([[0], np.cumsum(np.bitwise_count(np.diff(g)).astype(np.int64))])
+    pref = np.concatenate([[0], np.cumsum(good.astype(np.int64))])
+    ok = window[:, 0] <= window[:, 1]
+    pa = pref[window[ok, 0]]
+    pb = pref[window[ok, 1] + 1]
+    m = pb - pa >= 2
+    return float((cp[pb[m] - 1] - cp[pa[m]]).sum())
+
+
+def wide_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> dict:
+    """d = 2^20 with |a_k| = 2^g, g ~ N(0, 40^2) (dense, and 1 % nonzero), 10^6
+    points, FP64 at p = 53 and p = 24: the window sums in the dense form
+    (Horner over every index, bad coefficients masked) and in the sparse form
+    (Horner over the list of G_p, gaps jumped by powers of z), each at its
+    fastest chunk length; evaluations/s, the window kernel's time and its
+    algorithmic fraction of the FP64 peak (8 flops per kept term, 6 per
+    product of z^l's powering and, in the sparse form, 6 per binary digit of
+    each gap), and the max scaled error against the oracle at the same p on a
+    seeded sample."""
+    out = {}
+    for name in ("wide_d2p20", "sparse_wide_d2p20"):
+        wl = workloads.workload(name)
+        c = torch.from_numpy(wl.coeffs).to(dev)
+        z = torch.from_numpy(wl.points).to(dev)
+        n = len(wl.points)
+        idx = np.random.default_rng(12348).choice(n, min(check, n), replace=False)
+        for p in (53, 24):
+            plan = fpe.precondition(c, p)
+            _, _, good = plan.export()
+            _, _, t, w = plan.eval(z, terms=True, window=True)
+            torch.cuda.synchronize()
+            terms, window = t.cpu().numpy(), w.cpu().numpy()
+            base = algorithmic_flops(terms, window)
+            digits = sparse_gap_digits(good, terms, window, np)
+            ref = oracle.precondition(wl.coeffs, p).eval(wl.points[idx])
+            row = {"d": wl.degree, "n_points": n, "p_bits": p, "kept_terms": int(terms.sum()),
+                   "window_indices": int((window[:, 1] - window[:, 0] + 1).clip(0).sum()), "gap_digits": digits}
+            mo = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+            for mode in ("dense", "sparse"):
+                plan.set_window_mode(mode)
+                best = None
+                for C in (256, 512, 1024, 2048):
+                    plan.set_chunk(C)
+                    plan.eval(z, out=mo)
+                    torch.cuda.synchronize()
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    for _ in range(3):
+                        plan.eval(z, out=mo)
+                    b.record()
+                    torch.cuda.synchronize()
+                    ms = a.elapsed_time(b) / 3
+                    if best is None or ms < best[1]:
+                        best = (C, ms)
+                plan.set_chunk(best[0])
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(steps):
+                    plan.eval(z, out=mo)
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / steps
+                fpe.profile_read()
+                fpe.profile_enable(True)
+                for _ in range(3):
+                    plan.eval(z, out=mo)
+                torch.cuda.synchronize()
+                fpe.profile_enable(False)
+                wms, k = fpe.profile_read()
+                wms /= max(k, 1)
+                flops = base + (6.0 * digits if mode == "sparse" else 0.0)
+                mm, ee = mo[0].cpu().numpy(), mo[1].cpu().numpy()
+                err = oracle.scaled_error(mm[idx], ee[idx], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+                row[mode] = {"chunk": best[0], "ms": ms, "value": n / (ms * 1e-3), "window_kernel_ms": wms,
+                             "algorithmic_flops": flops,
+                             "frac_fp64_peak": flops / (wms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                             "max_scaled_err": float(err.max())}
+            log(f"{name} p={p}: dense {row['dense']['ms']:.3f} ms (window {row['dense']['window_kernel_ms']:.3f}, "
+                f"C={row['dense']['chunk']}), sparse {row['sparse']['ms']:.3f} ms "
+                f"(window {row['sparse']['window_kernel_ms']:.3f}, C={row['sparse']['chunk']}); kept terms "
+                f"{row['kept_terms']:.3e} of {row['window_indices']:.3e} window indices; max err dense "
+                f"{row['dense']['max_scaled_err']:.2e} sparse {row['sparse']['max_scaled_err']:.2e}")
+            out[f"{name}_p{p}"] = row
+    out["unit"] = "evaluations/s"
+    out["tolerance"] = 2.0 ** -44
+    return out
+
+
 def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
     """4096 polynomials, degrees log-uniform in [16, 65536], 64..1024 spherical
     points each (FP64, p = 53): preconditioning of every plan (timed apart),
@@ -166,8 +260,17 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
     points, eagerly and as a replayed HIP graph, beside one fpe_eval per
     polynomial in a loop."""
     coeffs, points = workloads.batched_workload()
+    cdev = [torch.from_numpy(c).to(dev) for c in coeffs]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plans = [fpe.precondition(torch.from_numpy(c).to(dev), 53) for c in coeffs]
+    loop_plans = [fpe.precondition(c, 53) for c in cdev]
+    torch.cuda.synchronize()
+    pre_loop_ms = (time.perf_counter() - t0) * 1e3
+    del loop_plans
+    fpe.precondition_batched(cdev[:8], 53)          # warm-up of the batched kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = fpe.precondition_batched(cdev, 53)
     torch.cuda.synchronize()
     pre_ms = (time.perf_counter() - t0) * 1e3
     offs = np.concatenate([[0], np.cumsum([len(z) for z in points])])
@@ -220,7 +323,8 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
         worst = max(worst, float(oracle.scaled_error(mm[sl], ee[sl], ref["m"], ref["e"], ref["dwin_m"],
                                                      ref["dwin_e"]).max()))
     log(f"batch of {len(plans)} polynomials, {n} points: eager {eager_ms:.3f} ms, graph replay {graph_ms:.3f} ms, "
-        f"per-polynomial loop {loop_ms:.1f} ms (chunk {chunk}); preconditioning {pre_ms:.0f} ms; "
+        f"per-polynomial loop {loop_ms:.1f} ms (chunk {chunk}); preconditioning {pre_ms:.1f} ms batched, "
+        f"{pre_loop_ms:.0f} ms one at a time; "
         f"max scaled error (16 polynomials) {worst:.2e}; {kept} kept terms, window kernel {win_ms:.3f} ms "
         f"({8 * kept / (win_ms * 1e-3) / 1e12:.2f} TFLOP/s in the kept terms' FMAs)")
     return {"workload": "batched_4096", "n_poly": len(plans), "n_points": n,
@@ -228,7 +332,8 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
             "eager": {"ms": eager_ms, "value": n / (eager_ms * 1e-3)},
             "graph_replay": {"ms": graph_ms, "value": n / (graph_ms * 1e-3)},
             "per_polynomial_loop": {"ms": loop_ms, "value": n / (loop_ms * 1e-3)},
-            "precondition_ms": pre_ms, "max_scaled_err_16_polys": worst,
+            "precondition_ms": pre_ms, "precondition_one_at_a_time_ms": pre_loop_ms,
+            "max_scaled_err_16_polys": worst,
             "kept_terms": kept, "window_kernel_ms": win_ms,
             "window_tflops_kept_terms": 8 * kept / (win_ms * 1e-3) / 1e12}
 
@@ -245,6 +350,7 @@ def main() -> int:
     ap.add_argument("--no-f3", action="store_true", help="skip the derivative / adjoint / Newton leg")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 (p = 24) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-polynomial leg")
+    ap.add_argument("--no-wide", action="store_true", help="skip the d = 2^20 wide-range leg (dense and sparse)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="chunk length of the tiles (0: autotuned before the timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=131072,
@@ -394,6 +500,8 @@ def main() -> int:
         res["adjoint_newton"] = adjoint_leg(fpe, workloads, torch, dev, args.steps)
     if not args.no_fp32:
         res["fp32_p24"] = fp32_leg(fpe, workloads, oracle, np, torch, dev, args.steps, args.check_sample)
+    if not args.no_wide:
+        res["wide_range"] = wide_leg(fpe, workloads, oracle, np, torch, dev, args.steps, args.check_sample)
     if not args.no_batched:
         res["batched"] = batched_leg(fpe, workloads, oracle, np, torch, dev, args.steps)
 

@@ -80,9 +80,23 @@ enum {
      * whose cover drops by more than 99 within the chunk), a wavefront holding
      * a point with |z| outside [2^-12, 2^12], the ragged start of windows
      * inside a tile.  Error bound: the FP32 block Horner contributes at most
-     * about 24 2^-24 sum |a_k||z|^k (8 steps, the rounding of z and of a_k);
-     * fpe_eval_deriv, fpe_newton_step and fpe_eval_adjoint stay in FP64. */
-    FPE_PRECONDITION_FP32 = 1u
+     * about 24 2^-24 sum |a_k||z|^k (8 steps, the rounding of z and of a_k).
+     * fpe_eval_deriv and fpe_newton_step sum Q and Q' the same way (the block
+     * derivatives accumulated as Q' <- Q' z^8 + 8 z^7 Q + block's); the reverse
+     * mode (fpe_eval_adjoint) stays in FP64.  Which tiles run in FP32 depends
+     * on the points sharing a wavefront, so the last bits of an FP32 plan's
+     * values can vary from call to call (within the bound). */
+    FPE_PRECONDITION_FP32 = 1u,
+    /* With FPE_PRECONDITION_FP32: each FP32 block runs the compensated Horner
+     * recurrence instead of the plain one: the products s z split exactly by
+     * TwoProd (fused multiply-add), the additions by TwoSum, and the lost parts
+     * (with the rounding error of z in FP32) carried in an FP32 correction
+     * term; the block's sum is the sum of the two.  The recurrence's error
+     * drops to a few units of 2^-48 per step; the rounding of the coefficients
+     * to FP32 (at most 2^-24 of each term) then bounds the error: about
+     * 2^-24 sum |a_k||z|^k.  About ten times the FP32 operations of the plain
+     * form; values only (fpe_eval_deriv runs the plain form). */
+    FPE_PRECONDITION_FP32_COMPENSATED = 2u
 };
 
 /* Bytes of device workspace fpe_precondition needs for a polynomial of degree
@@ -119,6 +133,64 @@ fpe_status fpe_precondition_workspace_size(int64_t d, int32_t p_bits, uint32_t f
 fpe_status fpe_precondition(const double *coef_dev, int64_t d, int32_t p_bits, uint32_t flags,
                             void *workspace_dev, size_t workspace_bytes,
                             hipStream_t stream, fpe_plan_t *out_plan);
+
+/* The two parts of preconditioning apart (Remark partialpreproc, Section 5.1:
+ * the concave cover does not depend on p, only G_p does): fpe_cover_build
+ * computes the scales and their concave cover once; fpe_plan_from_cover then
+ * finishes a plan for a precision p (G_p and the tables, in O(d)) as often as
+ * needed, e.g. for p = 53 and p = 24.  A plan from a cover is bit for bit the
+ * plan fpe_precondition builds from the same coefficients and p. */
+typedef struct fpe_cover_s *fpe_cover_t;
+
+/* Bytes of device workspace fpe_cover_build needs for degree d. */
+fpe_status fpe_cover_workspace_size(int64_t d, size_t *bytes);
+
+/* The scales s(a_k) and their concave cover (Algorithm A_p, lines 2-3), in
+ * workspace_dev (caller-owned, 256-byte aligned, borrowed by the cover: keep
+ * it until fpe_cover_destroy).  coef_dev as fpe_precondition (only read here).
+ * The call waits for stream.  Errors: FPE_ERR_INVALID_ARG, FPE_ERR_WORKSPACE,
+ * FPE_ERR_NONFINITE, FPE_ERR_HIP. */
+fpe_status fpe_cover_build(const double *coef_dev, int64_t d, void *workspace_dev, size_t workspace_bytes,
+                           hipStream_t stream, fpe_cover_t *out_cover);
+
+/* Cover summary, written to info_host[0..4]: d, v (first nonzero index, -1 if
+ * P == 0), d' (last nonzero index), number of cover vertices, max s(a_k). */
+fpe_status fpe_cover_info(fpe_cover_t cover, int64_t *info_host);
+
+/* Frees the host handle (the workspace stays the caller's). */
+fpe_status fpe_cover_destroy(fpe_cover_t cover);
+
+/* Bytes of device workspace fpe_plan_from_cover needs (p_bits and flags as
+ * fpe_precondition). */
+fpe_status fpe_plan_from_cover_workspace_size(fpe_cover_t cover, int32_t p_bits, uint32_t flags, size_t *bytes);
+
+/* Finishes the preconditioning for precision p_bits (Algorithm A_p, line 4):
+ * G_p and the tables of a plan, in workspace_dev (caller-owned, 256-byte
+ * aligned, borrowed by the plan).  coef_dev must hold the coefficients the
+ * cover was built from (read again here; not checked).  The plan copies the
+ * cover's vertices: the cover may be destroyed afterwards.  The call waits for
+ * stream.  Arguments otherwise and errors as fpe_precondition. */
+fpe_status fpe_plan_from_cover(fpe_cover_t cover, const double *coef_dev, int32_t p_bits, uint32_t flags,
+                               void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                               fpe_plan_t *out_plan);
+
+/* Many polynomials preconditioned by one launch sequence and one wait:
+ * polynomial i has the coefficients coef_dev[2 off[i] .. 2 off[i+1] - 1]
+ * (complex, a_0 first; off = coef_offsets_host, n_poly + 1 host int64,
+ * off[0] = 0, at least one coefficient each).  Polynomials of at most 2^17
+ * coefficients are preconditioned by one workgroup each, all in one launch;
+ * larger ones by the per-coefficient kernels of fpe_precondition, on the same
+ * stream.  plans_out (host array of n_poly handles) receives ordinary plans,
+ * bit for bit those of fpe_precondition, each borrowing its part of
+ * workspace_dev (caller-owned, 256-byte aligned, at least the queried size);
+ * destroy each with fpe_plan_destroy.  p_bits and flags apply to every
+ * polynomial.  On an error no plan is returned, and the message names the
+ * first failing polynomial.  Errors as fpe_precondition. */
+fpe_status fpe_precondition_batched_workspace_size(int32_t n_poly, const int64_t *coef_offsets_host,
+                                                   int32_t p_bits, uint32_t flags, size_t *bytes);
+fpe_status fpe_precondition_batched(const double *coef_dev, const int64_t *coef_offsets_host, int32_t n_poly,
+                                    int32_t p_bits, uint32_t flags, void *workspace_dev, size_t workspace_bytes,
+                                    hipStream_t stream, fpe_plan_t *plans_out);
 
 /* Plan summary, written to info_host[0..9]:
  *   0 d (as given)      1 v (first nonzero index, -1 if P == 0)
@@ -337,12 +409,39 @@ fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, double *m_de
  * FPE_ERR_INVALID_ARG. */
 fpe_status fpe_plan_set_chunk(fpe_plan_t plan, int32_t chunk);
 
+/* The form of fpe_eval's window sums (Section 5.2 sums the kept terms a_k z^k,
+ * k in G_p within [l, r]; both forms sum exactly those terms):
+ *   FPE_WINDOW_DENSE   Horner's rule over every index of the window, the
+ *                      coefficients outside G_p masked to 0 (work ~ r - l + 1);
+ *   FPE_WINDOW_SPARSE  Horner's rule over the list of G_p inside the window,
+ *                      each gap between two consecutive indices jumped by the
+ *                      powers z^(2^j) of its binary digits (the precomputed
+ *                      powers of the paper's implementation notes, Section 8.2;
+ *                      work ~ #(G_p within [l, r]) times the digits per gap).
+ * fpe_eval_deriv, fpe_newton_step, fpe_eval_adjoint and batches run the dense
+ * form; FP32 plans run the dense form only. */
+enum { FPE_WINDOW_AUTO = 0, FPE_WINDOW_DENSE = 1, FPE_WINDOW_SPARSE = 2 };
+
+/* Sets the window-sum form of later fpe_eval calls on this plan: one of the
+ * FPE_WINDOW_* values (AUTO: the form fpe_autotune found for the same bucket
+ * of degree, point count and |G_p| earlier in this process, else DENSE).
+ * Errors: FPE_ERR_INVALID_ARG (NULL plan, unknown mode), FPE_ERR_UNSUPPORTED
+ * (SPARSE on an FP32 plan). */
+fpe_status fpe_plan_set_window_mode(fpe_plan_t plan, int32_t mode);
+
+/* The chunk length and the window-sum form (FPE_WINDOW_DENSE or
+ * FPE_WINDOW_SPARSE) an fpe_eval of n points on this plan would use now.
+ * Either output pointer (host) may be NULL.  Errors: FPE_ERR_INVALID_ARG. */
+fpe_status fpe_plan_tile_choice(fpe_plan_t plan, int64_t n, int32_t *chunk_out, int32_t *mode_out);
+
 /* Times fpe_eval of these n points (writing m, e as fpe_eval does) with each
- * candidate chunk length 256, 512, 1024, 2048 (one untimed and three timed
- * calls each, HIP events on stream; the call waits), keeps the fastest for this
- * plan, records it for the plan's bucket (bit length of d, bit length of n) in a
- * process-wide cache that untuned plans consult, and writes it to *chunk_out
- * (may be NULL).  FP32 plans keep 512.  Arguments and errors as fpe_eval. */
+ * candidate chunk length 256, 512, 1024, 2048 in each window-sum form (one
+ * untimed and three timed calls each, HIP events on stream; the call waits),
+ * keeps the fastest pair for this plan, records it for the plan's bucket (bit
+ * lengths of d, n and |G_p|) in a process-wide cache that untuned plans
+ * consult, and writes the chunk length to *chunk_out (may be NULL); the form is
+ * readable with fpe_plan_tile_choice.  FP32 plans keep 512 and the dense form.
+ * Arguments and errors as fpe_eval. */
 fpe_status fpe_autotune(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
                         void *workspace_dev, size_t workspace_bytes, hipStream_t stream, int32_t *chunk_out);
 

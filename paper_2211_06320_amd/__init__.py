@@ -14,6 +14,8 @@ There is no fallback: if libfpe.so is missing, loading fails with an error.
     m, e, md, ed = plan.eval_deriv(z)      # and Q' = md * 2**ed through the same window
     ga, gz = plan.adjoint(z, g)            # reverse mode for upstream gradients g
     q = fpe_eval(coeffs, z)                # differentiable (torch.autograd)
+    cov = Cover(coeffs); p53, p24 = cov.plan(53), cov.plan(24)    # the cover once, G_p per precision
+    plans = precondition_batched([c1, c2, c3])                      # many polynomials, one launch sequence
     b = Batch([plan_a, plan_b], [0, na, na + nb]); m, e = b.eval(z_ab)   # many polynomials at once
 """
 from __future__ import annotations
@@ -29,6 +31,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fpe.h")
 
 FPE_OK = 0
 PRECONDITION_FP32 = 1
+PRECONDITION_FP32_COMPENSATED = 2
+WINDOW_AUTO, WINDOW_DENSE, WINDOW_SPARSE = 0, 1, 2
 STATUS = {0: "FPE_OK", 1: "FPE_ERR_INVALID_ARG", 2: "FPE_ERR_NONFINITE", 3: "FPE_ERR_PRECISION",
           4: "FPE_ERR_WORKSPACE", 5: "FPE_ERR_HIP", 6: "FPE_ERR_UNSUPPORTED"}
 
@@ -67,6 +71,22 @@ def lib() -> ctypes.CDLL:
     L.fpe_precondition_workspace_size.argtypes = [i64, i32, u32, P(sz)]
     L.fpe_precondition.restype = i32
     L.fpe_precondition.argtypes = [vp, i64, i32, u32, vp, sz, vp, P(vp)]
+    L.fpe_cover_workspace_size.restype = i32
+    L.fpe_cover_workspace_size.argtypes = [i64, P(sz)]
+    L.fpe_cover_build.restype = i32
+    L.fpe_cover_build.argtypes = [vp, i64, vp, sz, vp, P(vp)]
+    L.fpe_cover_info.restype = i32
+    L.fpe_cover_info.argtypes = [vp, P(i64)]
+    L.fpe_cover_destroy.restype = i32
+    L.fpe_cover_destroy.argtypes = [vp]
+    L.fpe_plan_from_cover_workspace_size.restype = i32
+    L.fpe_plan_from_cover_workspace_size.argtypes = [vp, i32, u32, P(sz)]
+    L.fpe_plan_from_cover.restype = i32
+    L.fpe_plan_from_cover.argtypes = [vp, vp, i32, u32, vp, sz, vp, P(vp)]
+    L.fpe_precondition_batched_workspace_size.restype = i32
+    L.fpe_precondition_batched_workspace_size.argtypes = [i32, P(i64), i32, u32, P(sz)]
+    L.fpe_precondition_batched.restype = i32
+    L.fpe_precondition_batched.argtypes = [vp, P(i64), i32, i32, u32, vp, sz, vp, P(vp)]
     L.fpe_plan_info.restype = i32
     L.fpe_plan_info.argtypes = [vp, P(i64)]
     L.fpe_plan_export.restype = i32
@@ -95,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.fpe_eval_batched.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_plan_set_chunk.restype = i32
     L.fpe_plan_set_chunk.argtypes = [vp, i32]
+    L.fpe_plan_set_window_mode.restype = i32
+    L.fpe_plan_set_window_mode.argtypes = [vp, i32]
+    L.fpe_plan_tile_choice.restype = i32
+    L.fpe_plan_tile_choice.argtypes = [vp, i64, P(i32), P(i32)]
     L.fpe_autotune.restype = i32
     L.fpe_autotune.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp, P(i32)]
     L.fpe_batch_set_chunk.restype = i32
@@ -131,6 +155,12 @@ def _stream(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+def _flags(fp32: bool, compensated: bool) -> int:
+    if compensated and not fp32:
+        raise ValueError("compensated FP32 blocks need fp32=True")
+    return (PRECONDITION_FP32 if fp32 else 0) | (PRECONDITION_FP32_COMPENSATED if compensated else 0)
+
+
 def _dev_complex(x, name):
     torch = _torch()
     if not isinstance(x, torch.Tensor) or x.dtype != torch.complex128 or not x.is_cuda:
@@ -163,22 +193,33 @@ class PlanInfo:
 class Plan:
     """A polynomial preconditioned by fpe_precondition (Algorithm A_p, first block)."""
 
-    def __init__(self, coeffs, p: int = 53, stream=None, fp32: bool = False):
+    def __init__(self, coeffs, p: int = 53, stream=None, fp32: bool = False, compensated: bool = False):
         L = lib()
         coeffs = _dev_complex(coeffs, "coeffs")
-        self.device = coeffs.device
-        self.d = coeffs.shape[0] - 1
-        self.fp32 = bool(fp32)
-        flags = PRECONDITION_FP32 if fp32 else 0
+        d = coeffs.shape[0] - 1
+        flags = _flags(fp32, compensated)
         nb = ctypes.c_size_t()
-        _check(L.fpe_precondition_workspace_size(self.d, p, flags, ctypes.byref(nb)))
-        self._ws_buf, ws = _workspace(nb.value, coeffs.device)
+        _check(L.fpe_precondition_workspace_size(d, p, flags, ctypes.byref(nb)))
+        ws_buf, ws = _workspace(nb.value, coeffs.device)
         h = ctypes.c_void_p()
-        _check(L.fpe_precondition(coeffs.data_ptr(), self.d, p, flags, ws, nb.value,
+        _check(L.fpe_precondition(coeffs.data_ptr(), d, p, flags, ws, nb.value,
                                   _stream(stream), ctypes.byref(h)))
+        self._adopt(h, ws_buf, coeffs.device, d, fp32)
+
+    def _adopt(self, h, ws_buf, device, d: int, fp32: bool):
         self._h = h
+        self._ws_buf = ws_buf                  # the plan's tables live here
+        self.device = device
+        self.d = int(d)
+        self.fp32 = bool(fp32)
         self._eval_ws = {}
-        self._destroy = L.fpe_plan_destroy     # kept: module globals may be gone at exit
+        self._destroy = lib().fpe_plan_destroy     # kept: module globals may be gone at exit
+
+    @classmethod
+    def _from_handle(cls, h, ws_buf, device, d: int, fp32: bool):
+        obj = cls.__new__(cls)
+        obj._adopt(h, ws_buf, device, d, fp32)
+        return obj
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -259,8 +300,21 @@ class Plan:
         """Chunk length of the tiles for later evaluations (0: automatic)."""
         _check(lib().fpe_plan_set_chunk(self._h, int(chunk)))
 
+    def set_window_mode(self, mode) -> None:
+        """Window-sum form of later evaluations: "auto", "dense" or "sparse"
+        (or WINDOW_AUTO / WINDOW_DENSE / WINDOW_SPARSE)."""
+        m = {"auto": WINDOW_AUTO, "dense": WINDOW_DENSE, "sparse": WINDOW_SPARSE}.get(mode, mode)
+        _check(lib().fpe_plan_set_window_mode(self._h, int(m)))
+
+    def tile_choice(self, n: int):
+        """(chunk length, "dense" or "sparse") an evaluation of n points would use."""
+        c, m = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fpe_plan_tile_choice(self._h, int(n), ctypes.byref(c), ctypes.byref(m)))
+        return c.value, ("sparse" if m.value == WINDOW_SPARSE else "dense")
+
     def autotune(self, z, stream=None) -> int:
-        """Times the candidate chunk lengths on these points, keeps the fastest."""
+        """Times the candidate chunk lengths and window-sum forms on these
+        points, keeps the fastest pair; returns the chunk length."""
         torch = _torch()
         z = _dev_complex(z, "z")
         n = z.shape[0]
@@ -460,9 +514,81 @@ def fpe_eval(coeffs, z, p: int = 53):
     return _FPE_FN.apply(_dev_complex(coeffs, "coeffs"), _dev_complex(z, "z"), p)
 
 
-def precondition(coeffs, p: int = 53, stream=None, fp32: bool = False) -> Plan:
-    """fp32=True (p <= 24): fpe_eval sums the windows in FP32 (FPE_PRECONDITION_FP32)."""
-    return Plan(coeffs, p, stream, fp32)
+class Cover:
+    """The scales and the concave cover of a polynomial (fpe_cover_build), which
+    do not depend on p; plan(p) finishes the preconditioning for a precision
+    (fpe_plan_from_cover: G_p and the tables), as often as needed."""
+
+    def __init__(self, coeffs, stream=None):
+        L = lib()
+        self.coeffs = _dev_complex(coeffs, "coeffs")     # kept: plan() reads them again
+        self.device = self.coeffs.device
+        self.d = self.coeffs.shape[0] - 1
+        nb = ctypes.c_size_t()
+        _check(L.fpe_cover_workspace_size(self.d, ctypes.byref(nb)))
+        self._ws_buf, ws = _workspace(nb.value, self.device)
+        h = ctypes.c_void_p()
+        _check(L.fpe_cover_build(self.coeffs.data_ptr(), self.d, ws, nb.value, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._destroy = L.fpe_cover_destroy
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            self._h = None
+
+    def info(self):
+        """(d, v, d', number of cover vertices, max s(a_k))."""
+        import numpy as np
+        out = np.zeros(5, np.int64)
+        _check(lib().fpe_cover_info(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return tuple(int(x) for x in out)
+
+    def plan(self, p: int = 53, fp32: bool = False, stream=None, compensated: bool = False) -> Plan:
+        L = lib()
+        flags = _flags(fp32, compensated)
+        nb = ctypes.c_size_t()
+        _check(L.fpe_plan_from_cover_workspace_size(self._h, p, flags, ctypes.byref(nb)))
+        ws_buf, ws = _workspace(nb.value, self.device)
+        h = ctypes.c_void_p()
+        _check(L.fpe_plan_from_cover(self._h, self.coeffs.data_ptr(), p, flags, ws, nb.value, _stream(stream),
+                                     ctypes.byref(h)))
+        return Plan._from_handle(h, ws_buf, self.device, self.d, fp32)
+
+
+def precondition_batched(coeffs, p: int = 53, fp32: bool = False, stream=None, compensated: bool = False) -> list:
+    """Plans for many polynomials from one launch sequence (fpe_precondition_batched).
+    coeffs: a list of complex128 CUDA tensors (a_0 first each).  The plans share
+    one workspace (held by each of them)."""
+    torch = _torch()
+    L = lib()
+    parts = [_dev_complex(c, "coeffs") for c in coeffs]
+    if not parts:
+        return []
+    flat = torch.cat(parts)
+    offs = [0]
+    for c in parts:
+        offs.append(offs[-1] + int(c.shape[0]))
+    n_poly = len(parts)
+    c_offs = (ctypes.c_int64 * len(offs))(*offs)
+    flags = _flags(fp32, compensated)
+    nb = ctypes.c_size_t()
+    _check(L.fpe_precondition_batched_workspace_size(n_poly, c_offs, p, flags, ctypes.byref(nb)))
+    ws_buf, ws = _workspace(nb.value, flat.device)
+    handles = (ctypes.c_void_p * n_poly)()
+    _check(L.fpe_precondition_batched(flat.data_ptr(), c_offs, n_poly, p, flags, ws, nb.value, _stream(stream),
+                                      handles))
+    return [Plan._from_handle(ctypes.c_void_p(handles[i]), ws_buf, flat.device, offs[i + 1] - offs[i] - 1, fp32)
+            for i in range(n_poly)]
+
+
+def precondition(coeffs, p: int = 53, stream=None, fp32: bool = False, compensated: bool = False) -> Plan:
+    """fp32=True (p <= 24): fpe_eval sums the windows in FP32 (FPE_PRECONDITION_FP32);
+    compensated=True with it: the FP32 blocks by the compensated (TwoSum/TwoProd)
+    recurrence (FPE_PRECONDITION_FP32_COMPENSATED)."""
+    return Plan(coeffs, p, stream, fp32, compensated)
 
 
 def horner_eval(coeffs, z, out=None, stream=None):

@@ -428,8 +428,15 @@ __device__ __forceinline__ int cost_units(int steps, int shift) {
 
 __device__ __forceinline__ int bit_length(int x) { return x > 0 ? 32 - __clz(x) : 0; }
 
-// glo, ghi: the group's union window; gml: its largest window start
-__device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C, int shift) {
+// the Horner steps of a tile part of len coefficients: all of them for a dense
+// window sum, the share dens / 256 for a sparse one
+__device__ __forceinline__ int tile_steps(int len, int dens) {
+    return dens >= 256 ? len : (int)(((long long)len * dens + 255) >> 8);
+}
+
+// glo, ghi: the group's union window; gml: its largest window start; dens: the
+// share of the union window's Horner steps the tiles run (256: dense)
+__device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C, int shift, int dens) {
     GroupCost gc;
     gc.clo = glo / C;
     gc.chi = ghi / C;
@@ -437,16 +444,17 @@ __device__ __forceinline__ GroupCost group_cost(int glo, int ghi, int gml, int C
     const int pow_start = kPowSteps * bit_length(gml);
     const int anchor = kAnchorBitSteps * bit_length(ghi);
     if (gc.chi == gc.clo) {
-        gc.first = gc.last = cost_units(ghi - glo + 1 + kTileSteps + pow_start, shift);
+        gc.first = gc.last = cost_units(tile_steps(ghi - glo + 1, dens) + kTileSteps + pow_start, shift);
         gc.ns = 0;
         gc.cs = gc.cn = 1;
         return gc;
     }
-    gc.first = cost_units(gc.clo * C + C - glo + kTileSteps + kFirstSteps + pow_start, shift);
-    gc.last = cost_units(ghi - gc.chi * C + 1 + kTileSteps + kLastSteps + anchor + (gc.chi <= cl ? pow_start : 0),
+    gc.first = cost_units(tile_steps(gc.clo * C + C - glo, dens) + kTileSteps + kFirstSteps + pow_start, shift);
+    gc.last = cost_units(tile_steps(ghi - gc.chi * C + 1, dens) + kTileSteps + kLastSteps + anchor +
+                             (gc.chi <= cl ? pow_start : 0),
                          shift);
     gc.ns = max(0, min(cl, gc.chi - 1) - gc.clo);
-    const int mid = C + C / 8 + kTileSteps + kMidSteps + anchor;
+    const int mid = tile_steps(C + C / 8, dens) + kTileSteps + kMidSteps + anchor;
     gc.cs = cost_units(mid + pow_start, shift);
     gc.cn = cost_units(mid, shift);
     return gc;
@@ -459,6 +467,7 @@ __device__ __forceinline__ long long group_total(const GroupCost &gc) {
 }
 
 constexpr int kGroupsPerBlock = 1024 / kWave;
+constexpr int kSparseSteps = 5;        // cost of one entry of a sparse window sum, in Horner steps
 
 // ---- many polynomials in one evaluation (fpe_eval_batched)
 constexpr int kBatchMaxPoints = 4096;   // points of one polynomial of a batch (sorted by one workgroup)
@@ -566,12 +575,21 @@ __global__ __launch_bounds__(1024) void k_groups(DevPlan P, EvalWs W) {
         // records without a window (a batch's padding and finished points) do not count
         if (idx < nvalid) { const PointRec &rc = W.srec[idx]; if (rc.l <= rc.r) { l = rc.l; r = rc.r; } }
         const int lo = wave_min(l), hi = wave_max(r), ml = wave_max(l != INT_MAX ? l : INT_MIN);
-        cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, W.chunk, W.cost_shift)) : 0;
+        int dens = 256;
+        if (W.sparse && hi >= lo) {
+            // a sparse window sum runs about kSparseSteps Horner steps per
+            // index of G_p in the union window
+            const long long u = (long long)P.gprefix[hi + 1] - P.gprefix[lo];
+            const long long w = (long long)hi - lo + 1;
+            dens = (int)min(256LL, max(1LL, (u * kSparseSteps * 256 + w - 1) / w));
+        }
+        cost = hi >= lo ? (int)group_total(group_cost(lo, hi, ml, W.chunk, W.cost_shift, dens)) : 0;
         if (lane == 0) {
             W.glo[g] = lo;
             W.ghi[g] = hi;
             W.gml[g] = ml;
             W.gcost[g] = cost;
+            W.gdens[g] = dens;
         }
     }
     if (lane == 0) s_cost[gw] = cost;
@@ -693,7 +711,7 @@ __device__ __forceinline__ void partition_wave(const EvalWs &W, const BlockOffse
     for (int k = 1; k < kGroupsPerBlock; ++k) g += (k < ng && base + cum[k] <= sw) ? 1 : 0;
     const long long A = base + W.gcum[g], B = A + W.gcost[g];
     if (sw >= B) { W.wstart[w] = make_int2(g + 1, -1); return; }
-    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
+    const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift, W.gdens[g]);
     const int2 st = wave_start(gc, g, A, B, sw);
     W.wstart[w] = st;
     // w starts inside g and g's first tile belongs to w - 1: g is split, and
@@ -735,7 +753,7 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
         if (cost == 0 || total == 0) {
             W.gwave[g] = make_int2(-1, -1);
         } else {
-            const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift);
+            const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift, W.gdens[g]);
             const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
             const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
             W.gwave[g] = gw;
@@ -882,53 +900,146 @@ __device__ __forceinline__ void step32(float &hr, float &hi, float zr, float zi,
     hi = fmaf(hi, zr, ti);
 }
 
-// H = sum over k = kto .. min(hi, kfrom) of a_k z^(k - kto), for the common and
-// top parts [kto, kfrom] of a tile (every active lane has lo <= kto): the
-// FP32 table in blocks of kBlock32 coefficients from the top, each block by a
-// plain FP32 Horner recurrence in z (lanes with hi below a coefficient add 0,
-// so their recurrence stays 0 until their part starts), and the block partials
-// by an FP64 Horner recurrence in z^8.  ktop: above it every lane takes every
-// step.  Returns H in the FP64 table's scale (times 2^sg).
-__device__ __forceinline__ void run_f32(double &Hr, double &Hi, float zr, float zi, double z8r, double z8i,
-                                        const_table32_t c32, int sg, int kfrom, int kto, int ktop, int hi) {
+// TwoSum in FP32: s + e = a + b exactly
+__device__ __forceinline__ void two_sum_f(float a, float b, float &s, float &e) {
+    FPE_NO_CONTRACT
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// One compensated FP32 Horner step (s, c) <- (s, c) z + a, z = zh + zl: the
+// products s zh split exactly by TwoProd (fmaf), the two additions of each
+// component by TwoSum, and the lost parts (product and sum errors, s zl) carried
+// in the correction c, itself advanced by c zh.  s + c is the sum with a
+// relative error of a few units of 2^-48 per step, far below the rounding of
+// the FP32 coefficients (2^-24) that bounds the form's accuracy.
+__device__ __forceinline__ void step32c(float &sr, float &si, float &cr, float &ci, float zhr, float zhi, float zlr,
+                                        float zli, float ar, float ai) {
+    FPE_NO_CONTRACT
+    const float p1 = sr * zhr, q1 = fmaf(sr, zhr, -p1);
+    const float p2 = si * zhi, q2 = fmaf(si, zhi, -p2);
+    const float p3 = sr * zhi, q3 = fmaf(sr, zhi, -p3);
+    const float p4 = si * zhr, q4 = fmaf(si, zhr, -p4);
+    float t1, e1, nr, e2, t2, e3, ni, e4;
+    two_sum_f(p1, -p2, t1, e1);
+    two_sum_f(t1, ar, nr, e2);
+    two_sum_f(p3, p4, t2, e3);
+    two_sum_f(t2, ai, ni, e4);
+    const float er = ((q1 - q2) + (e1 + e2)) + fmaf(sr, zlr, -(si * zli));
+    const float ei = ((q3 + q4) + (e3 + e4)) + fmaf(sr, zli, si * zlr);
+    const float ncr = fmaf(cr, zhr, fmaf(-ci, zhi, er));
+    ci = fmaf(cr, zhi, fmaf(ci, zhr, ei));
+    cr = ncr;
+    sr = nr;
+    si = ni;
+}
+
+// z in the forms the FP32 blocks use: FP32 z (and its rounding error, for the
+// compensated form), and z^8 and 8 z^7 in FP64 for the block accumulation
+struct Z32 { float r, i, lr, li; double z8r, z8i, z7r, z7i; };
+
+__device__ __forceinline__ Z32 make_z32(double zr, double zi) {
+    FPE_NO_CONTRACT
+    Z32 q;
+    q.r = (float)zr;
+    q.i = (float)zi;
+    q.lr = (float)(zr - (double)q.r);
+    q.li = (float)(zi - (double)q.i);
+    const double z2r = fma(zr, zr, -(zi * zi)), z2i = 2.0 * zr * zi;
+    const double z3r = fma(z2r, zr, -(z2i * zi)), z3i = fma(z2r, zi, z2i * zr);
+    const double z4r = fma(z2r, z2r, -(z2i * z2i)), z4i = 2.0 * z2r * z2i;
+    q.z8r = fma(z4r, z4r, -(z4i * z4i));
+    q.z8i = 2.0 * z4r * z4i;
+    q.z7r = 8.0 * fma(z4r, z3r, -(z4i * z3i));
+    q.z7i = 8.0 * fma(z4r, z3i, z4i * z3r);
+    return q;
+}
+
+// the FP32 recurrence of one block of L coefficients from A (a_{kt - L + 1}
+// .. a_{kt}, interleaved), from the top; lanes above their part add 0 (their
+// recurrence stays 0 until the part starts).  Returns the block's sum h (and
+// with D its derivative d) as doubles.
+template <bool D, bool COMP, int L>
+__device__ __forceinline__ void block32(const float *A, int kt, int hi, bool masked, const Z32 &z, double &br,
+                                        double &bi, double &dr, double &di) {
+    float hr = 0.0f, hh = 0.0f, cr = 0.0f, ch = 0.0f, gr = 0.0f, gh = 0.0f;
+#pragma unroll
+    for (int s2 = L - 1; s2 >= 0; --s2) {
+        const bool on = !masked || kt - (L - 1 - s2) <= hi;
+        const float ar = on ? A[2 * s2] : 0.0f, ai = on ? A[2 * s2 + 1] : 0.0f;
+        if constexpr (D) {
+            const float tr = fmaf(-gh, z.i, hr), ti = fmaf(gr, z.i, hh);
+            gr = fmaf(gr, z.r, tr);
+            gh = fmaf(gh, z.r, ti);
+        }
+        if constexpr (COMP) step32c(hr, hh, cr, ch, z.r, z.i, z.lr, z.li, ar, ai);
+        else step32(hr, hh, z.r, z.i, ar, ai);
+    }
+    br = COMP ? (double)hr + (double)cr : (double)hr;
+    bi = COMP ? (double)hh + (double)ch : (double)hh;
+    dr = (double)gr;
+    di = (double)gh;
+}
+
+// H = sum over k = kto .. min(hi, kfrom) of a_k z^(k - kto) (and with D its
+// derivative in z), for the common and top parts [kto, kfrom] of a tile (every
+// active lane has lo <= kto): the FP32 table in blocks of kBlock32
+// coefficients from the top, each block by an FP32 Horner recurrence in z
+// (plain, or with COMP compensated: TwoSum/TwoProd error terms carried in a
+// correction), and the block partials by an FP64 Horner recurrence in z^8
+// (H' <- H' z^8 + 8 z^7 H + block's derivative).  ktop: above it every lane
+// takes every step.  Returns H in the FP64 table's scale (times 2^sg).
+template <bool D, bool COMP>
+__device__ __forceinline__ void run_f32(Acc<D> &acc, const Z32 &z, const_table32_t c32, int sg, int kfrom, int kto,
+                                        int ktop, int hi) {
     FPE_NO_CONTRACT
     const int len = kfrom - kto + 1;
     const int l0 = len % kBlock32;
-    Hr = 0.0;
-    Hi = 0.0;
+    double Hr = 0.0, Hi = 0.0, Dr = 0.0, Di = 0.0;
     int k = kfrom;
-    if (l0 > 0) {                              // the short block at the top
-        float hr = 0.0f, hh = 0.0f;
-        for (int j = 0; j < l0; ++j, --k) {
-            const float ar = c32[2 * k], ai = c32[2 * k + 1];
-            const bool on = k <= hi;
-            step32(hr, hh, zr, zi, on ? ar : 0.0f, on ? ai : 0.0f);
+    if (l0 > 0) {                              // the short block at the top: H starts there
+        float hr = 0.0f, hh = 0.0f, cr = 0.0f, ch = 0.0f, gr = 0.0f, gh = 0.0f;
+        for (int j = 0; j < l0; ++j) {
+            const int kk = k - j;
+            const bool on = kk <= hi;
+            const float ar = on ? c32[2 * kk] : 0.0f, ai = on ? c32[2 * kk + 1] : 0.0f;
+            if constexpr (D) {
+                const float tr = fmaf(-gh, z.i, hr), ti = fmaf(gr, z.i, hh);
+                gr = fmaf(gr, z.r, tr);
+                gh = fmaf(gh, z.r, ti);
+            }
+            if constexpr (COMP) step32c(hr, hh, cr, ch, z.r, z.i, z.lr, z.li, ar, ai);
+            else step32(hr, hh, z.r, z.i, ar, ai);
         }
-        Hr = (double)hr;
-        Hi = (double)hh;
+        Hr = COMP ? (double)hr + (double)cr : (double)hr;
+        Hi = COMP ? (double)hh + (double)ch : (double)hh;
+        Dr = (double)gr;
+        Di = (double)gh;
+        k -= l0;
     }
     for (; k >= kto; k -= kBlock32) {          // full blocks [k - 7, k]
         const_table32_t p = c32 + 2 * (k - kBlock32 + 1);
         float A[2 * kBlock32];
 #pragma unroll
         for (int q = 0; q < 2 * kBlock32; ++q) A[q] = p[q];
-        float hr = 0.0f, hh = 0.0f;
-        if (k > ktop) {
-#pragma unroll
-            for (int s2 = kBlock32 - 1; s2 >= 0; --s2) {
-                const bool on = k - (kBlock32 - 1 - s2) <= hi;
-                step32(hr, hh, zr, zi, on ? A[2 * s2] : 0.0f, on ? A[2 * s2 + 1] : 0.0f);
-            }
-        } else {
-#pragma unroll
-            for (int s2 = kBlock32 - 1; s2 >= 0; --s2) step32(hr, hh, zr, zi, A[2 * s2], A[2 * s2 + 1]);
+        double br, bi, dr, di;
+        block32<D, COMP, kBlock32>(A, k, hi, k > ktop, z, br, bi, dr, di);
+        if constexpr (D) {
+            const double nr = fma(Dr, z.z8r, fma(-Di, z.z8i, fma(Hr, z.z7r, fma(-Hi, z.z7i, dr))));
+            Di = fma(Dr, z.z8i, fma(Di, z.z8r, fma(Hr, z.z7i, fma(Hi, z.z7r, di))));
+            Dr = nr;
         }
-        const double nr = fma(Hr, z8r, fma(-Hi, z8i, (double)hr));
-        Hi = fma(Hr, z8i, fma(Hi, z8r, (double)hh));
+        const double nr = fma(Hr, z.z8r, fma(-Hi, z.z8i, br));
+        Hi = fma(Hr, z.z8i, fma(Hi, z.z8r, bi));
         Hr = nr;
     }
-    Hr = ldexp(Hr, sg);
-    Hi = ldexp(Hi, sg);
+    acc.hr = ldexp(Hr, sg);
+    acc.hi = ldexp(Hi, sg);
+    if constexpr (D) {
+        acc.dr = ldexp(Dr, sg);
+        acc.di = ldexp(Di, sg);
+    }
 }
 
 constexpr int kWindowThreads = 256;
@@ -1008,11 +1119,15 @@ __device__ __forceinline__ long long deriv_eref(long long eref, int ez, int r) {
 // (fix_lo more bits), summed exactly across chunks
 // The fields of a polynomial's plan that the tile kernels read per group: of the
 // kernel's plan, or in a batch of the group's own plan (scalar loads).
+typedef const FPE_CONST_AS int32_t *const_itable_t;
 struct SegPlan {
     const_table_t cf;
     const_table32_t c32;
-    const FPE_CONST_AS int32_t *sig32;
+    const_itable_t sig32;
     int coef_shift, fix_shift, fix_lo;
+    const_itable_t gprefix, gidx;    // G_p as prefix counts and as a list (sparse window sums)
+    const_table_t gcoef;
+    int f32comp;                     // FP32 blocks compensated (TwoSum/TwoProd)
 };
 typedef const FPE_CONST_AS DevPlan *const_plans_t;
 
@@ -1021,12 +1136,226 @@ __device__ __forceinline__ SegPlan group_plan(const DevPlan &P, const EvalWs &W,
     if constexpr (B) {
         const int gp = __builtin_amdgcn_readfirstlane(W.gpoly[g]);
         const_plans_t pl = (const_plans_t)W.plans;
-        return {(const_table_t)pl[gp].coef, (const_table32_t)pl[gp].coef32,
-                (const FPE_CONST_AS int32_t *)pl[gp].sig32, pl[gp].coef_shift, pl[gp].fix_shift, pl[gp].fix_lo};
+        return {(const_table_t)pl[gp].coef, (const_table32_t)pl[gp].coef32, (const_itable_t)pl[gp].sig32,
+                pl[gp].coef_shift, pl[gp].fix_shift, pl[gp].fix_lo, (const_itable_t)pl[gp].gprefix,
+                (const_itable_t)pl[gp].gidx, (const_table_t)pl[gp].gcoef, pl[gp].f32comp};
     } else {
-        return {(const_table_t)P.coef, (const_table32_t)P.coef32, (const FPE_CONST_AS int32_t *)P.sig32,
-                P.coef_shift, P.fix_shift, P.fix_lo};
+        return {(const_table_t)P.coef, (const_table32_t)P.coef32, (const_itable_t)P.sig32,
+                P.coef_shift, P.fix_shift, P.fix_lo, (const_itable_t)P.gprefix, (const_itable_t)P.gidx,
+                (const_table_t)P.gcoef, P.f32comp};
     }
+}
+
+// ---- sparse window sums: Horner's rule over the list of G_p, each gap between
+// two consecutive indices jumped by powers of z (the precomputed powers of the
+// paper's implementation notes, Section 8.2, for lacunary windows).  A gap
+// inside a chunk is below kChunkMax = 2^11, so z^(2^j), j < 11, suffice.
+constexpr int kGapBits = 11;
+constexpr int kSparseRun = 16;        // list entries of a run, at least (see sparse_tile)
+constexpr int kSparseRunShift = 8;    // a run ends only between blocks of 2^8 indices
+
+// z^(2^j) = (tr[j] + i ti[j]) 2^f[j] for j < nb, with max(|tr|, |ti|) in
+// [1/2, 1] (rounded once from complex double-double squarings: relative error
+// one rounding); t_0 = w 2^ez = z exactly
+struct GapPowers { double tr[kGapBits], ti[kGapBits]; int f[kGapBits]; };
+
+__device__ __forceinline__ void gap_powers(double wr, double wi, int ez, int nb, GapPowers &T) {
+    T.tr[0] = wr;
+    T.ti[0] = wi;
+    T.f[0] = ez;
+    CDD x = {wr, 0.0, wi, 0.0};
+    long long ex = 0;
+#pragma unroll
+    for (int j = 1; j < kGapBits; ++j) {
+        if (j < nb) {
+            FPE_NO_CONTRACT
+            x = cdd_sqr(x);
+            ex *= 2;
+            cdd_renorm(x, ex);
+            T.tr[j] = x.rh + x.rl;
+            T.ti[j] = x.ih + x.il;
+            T.f[j] = (int)(ex + (long long)ez * (1LL << j));
+        } else {
+            T.tr[j] = 0.0;
+            T.ti[j] = 0.0;
+            T.f[j] = 0;
+        }
+    }
+}
+
+// (hr + i hi) 2^E <- (hr + i hi) 2^E z^(2^j)
+__device__ __forceinline__ void gap_mul(double &hr, double &hi, int &E, const GapPowers &T, int j) {
+    const double nr = fma(hr, T.tr[j], -(hi * T.ti[j]));
+    hi = fma(hr, T.ti[j], hi * T.tr[j]);
+    hr = nr;
+    E += T.f[j];
+}
+
+// One entry (k, a_k) of a sparse window sum for this lane: the gap from the
+// previous entry taken (z^gap by the binary digits of the wave-uniform gap),
+// then a_k 2^-e where k lies in the lane's part [lo, hi].  Returns whether the
+// lane ends its run before taking k (see sparse_tile).
+__device__ __forceinline__ bool sparse_entry(const GapPowers &T, int k, double ar, double ai, int kprev, int lo,
+                                             int hi, bool act, double &hr, double &hi_, int &e, int &kl, int &cnt) {
+    const bool in = act && k >= lo && k <= hi;
+    const bool mul = in && kl >= 0;
+    // a run ends where it has kSparseRun entries and the next one lies in
+    // another block of 2^kSparseRunShift indices than its last (a test on the
+    // lane's own entries, so the runs do not depend on the other lanes)
+    const bool brk = mul && cnt >= kSparseRun && (k >> kSparseRunShift) != (kl >> kSparseRunShift);
+    if (brk) return true;
+    const int gap = kprev - k;
+    if (__ballot(mul) != 0) {
+#pragma unroll
+        for (int j = 0; j < kGapBits; ++j) {
+            if ((gap >> j) == 0) break;
+            if ((gap >> j) & 1)
+                if (mul) gap_mul(hr, hi_, e, T, j);
+        }
+    }
+    if (in) {
+        hr += ldexp(ar, -e);
+        hi_ += ldexp(ai, -e);
+        kl = k;
+        ++cnt;
+    }
+    return false;
+}
+
+// the running sum's mantissa folded into E (exact: a power of two moves)
+__device__ __forceinline__ void sparse_renorm(double &Hr, double &Hi, int &E) {
+    const double mx = fmax(fabs(Hr), fabs(Hi));
+    if (mx != 0.0) {
+        const int ex = exp_of(mx);
+        Hr = ldexp(Hr, -ex);
+        Hi = ldexp(Hi, -ex);
+        E += ex;
+    }
+}
+
+constexpr int kSpBatch = 4;   // list entries per scalar-load batch (16 B of indices, 64 B of coefficients)
+
+__device__ __forceinline__ void load_entries(int *K, double *A, const_itable_t gidx, const_table_t gcoef, int i0) {
+#pragma unroll
+    for (int q = 0; q < kSpBatch; ++q) K[q] = gidx[i0 + q];
+#pragma unroll
+    for (int q = 0; q < 2 * kSpBatch; ++q) A[q] = gcoef[2 * i0 + q];
+}
+
+// Ends a run of a sparse window sum (lanes with go): the run's sum
+// (hr + i hi) 2^e, relative to the lowest index kl it took, carried down to lo
+// (z^(kl - lo) by the binary digits of kl - lo < 2^nb) and added to the tile's
+// sum (Hr + i Hi) 2^E; the run restarts empty.
+__device__ __forceinline__ void sparse_flush(const GapPowers &T, int nb, int lo, bool go, double &hr, double &hi,
+                                             int &e, int &kl, int &cnt, double &Hr, double &Hi, int &E) {
+    if (!go) return;
+    if (kl >= 0) {
+        const int g2 = kl - lo;
+#pragma unroll
+        for (int j = 0; j < kGapBits; ++j)
+            if (j < nb && ((g2 >> j) & 1)) gap_mul(hr, hi, e, T, j);
+        if (Hr == 0.0 && Hi == 0.0) {
+            Hr = hr; Hi = hi; E = e;
+        } else {
+            // both sums are renormalised: the sum of the tile's terms stays
+            // within the window's range, and a part below 2^-2000 of it is lost
+            const int sh = max(-2100, min(2100, e - E));
+            Hr += ldexp(hr, sh);
+            Hi += ldexp(hi, sh);
+        }
+        sparse_renorm(Hr, Hi, E);
+    }
+    hr = 0.0;
+    hi = 0.0;
+    e = 0;
+    kl = -1;
+    cnt = 0;
+}
+
+// The sparse form of one tile: H 2^E = sum over k in G_p within this lane's
+// part [lo, hi] of the chunk of a_k z^(k - lo).  The indices of G_p within
+// the tile's union part [Klo, Khi] are wave-uniform: their list entries come
+// through the scalar cache in batches of kSpBatch, two batches in flight (as
+// the dense steps' coefficients), from the top.  A lane takes the entries
+// inside its part: z^gap between two of them by the binary digits of the gap
+// (a product by z^(2^j) per digit), then the coefficient scaled by 2^-e.  The
+// running sum keeps its binary exponent e apart (renormalised after every
+// batch: exact), so no power of z need fit the double range on its own.  The
+// rounded powers z^(2^j) are reused along the recurrence, so their rounding
+// errors add up: a lane's entries are cut into runs (at least kSparseRun
+// entries, ending at a block boundary of 2^kSparseRunShift indices, decided
+// on the lane's own entries), each carried down to lo and added to the
+// tile's sum, so a term passes through at most about kSparseRun + 2^8 gaps
+// and one carry whatever the chunk length, and each lane's arithmetic does not
+// depend on the other lanes.
+__device__ __forceinline__ void sparse_tile(const SegPlan &S, const GapPowers &T, int nb, int Klo, int Khi, int lo,
+                                            int hi, bool act, double &Hr, double &Hi, int &E) {
+    Hr = 0.0;
+    Hi = 0.0;
+    E = 0;
+    double hr_ = 0.0, hi_ = 0.0;                  // the current run
+    int e_ = 0;
+    int kl = -1;                                   // the lowest index this lane took in the run
+    int cnt = 0;                                   //   and the entries it took
+    const int pa = __builtin_amdgcn_readfirstlane(S.gprefix[Klo]);
+    const int pb = __builtin_amdgcn_readfirstlane(S.gprefix[Khi + 1]);
+    if (pb <= pa) return;
+    int kprev = Khi + 1;                           // the first entry takes no gap (kl < 0 everywhere)
+    const int nfull = (pb - pa) / kSpBatch;
+    if (nfull > 0) {
+        // batch b holds the entries [pb - kSpBatch (b + 1), pb - kSpBatch b)
+        int KA[kSpBatch], KB[kSpBatch];
+        double AA[2 * kSpBatch], AB[2 * kSpBatch];
+        load_entries(KA, AA, S.gidx, S.gcoef, pb - kSpBatch);
+        for (int bi = 0; bi < nfull; bi += 2) {
+            wait_scalar_loads();
+            __builtin_amdgcn_sched_barrier(0);
+            if (bi + 1 < nfull) load_entries(KB, AB, S.gidx, S.gcoef, pb - kSpBatch * (bi + 2));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = kSpBatch - 1; q >= 0; --q) {
+                const bool brk = sparse_entry(T, KA[q], AA[2 * q], AA[2 * q + 1], kprev, lo, hi, act, hr_, hi_, e_,
+                                              kl, cnt);
+                if (__ballot(brk) != 0) {
+                    sparse_flush(T, nb, lo, brk, hr_, hi_, e_, kl, cnt, Hr, Hi, E);
+                    sparse_entry(T, KA[q], AA[2 * q], AA[2 * q + 1], kprev, lo, hi, act && brk, hr_, hi_, e_,
+                                 kl, cnt);
+                }
+                kprev = KA[q];
+            }
+            sparse_renorm(hr_, hi_, e_);
+            if (bi + 1 < nfull) {
+                wait_scalar_loads();
+                __builtin_amdgcn_sched_barrier(0);
+                if (bi + 2 < nfull) load_entries(KA, AA, S.gidx, S.gcoef, pb - kSpBatch * (bi + 3));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = kSpBatch - 1; q >= 0; --q) {
+                    const bool brk = sparse_entry(T, KB[q], AB[2 * q], AB[2 * q + 1], kprev, lo, hi, act, hr_, hi_, e_,
+                                                  kl, cnt);
+                    if (__ballot(brk) != 0) {
+                        sparse_flush(T, nb, lo, brk, hr_, hi_, e_, kl, cnt, Hr, Hi, E);
+                        sparse_entry(T, KB[q], AB[2 * q], AB[2 * q + 1], kprev, lo, hi, act && brk, hr_, hi_, e_,
+                                     kl, cnt);
+                    }
+                    kprev = KB[q];
+                }
+                sparse_renorm(hr_, hi_, e_);
+            }
+        }
+    }
+    // the lowest (pb - pa) mod kSpBatch entries one by one
+    for (int i = pb - kSpBatch * nfull - 1; i >= pa; --i) {
+        const int k = S.gidx[i];
+        const double ar = S.gcoef[2 * i], ai = S.gcoef[2 * i + 1];
+        const bool brk = sparse_entry(T, k, ar, ai, kprev, lo, hi, act, hr_, hi_, e_, kl, cnt);
+        if (__ballot(brk) != 0) {
+            sparse_flush(T, nb, lo, brk, hr_, hi_, e_, kl, cnt, Hr, Hi, E);
+            sparse_entry(T, k, ar, ai, kprev, lo, hi, act && brk, hr_, hi_, e_, kl, cnt);
+        }
+        kprev = k;
+    }
+    sparse_flush(T, nb, lo, true, hr_, hi_, e_, kl, cnt, Hr, Hi, E);
 }
 
 __device__ __forceinline__ void fix_add(const SegPlan &P, double qr, double qi, long long E, long long eref,
@@ -1056,8 +1385,12 @@ __device__ __forceinline__ void fix_out(int fix_shift, int fix_lo, long long a0,
 
 // With D, the same pass also sums the derivative of the kept terms,
 // Q'(z) = sum k a_k z^(k-1) over G_p within [l, r], into (md_out, ed_out).
-template <bool D, bool B>
-__global__ __launch_bounds__(kWindowThreads) __attribute__((amdgpu_waves_per_eu(D ? 5 : 6)))
+// With SP, each tile runs the sparse form (sparse_tile) instead of Horner's
+// rule over every index.  With FC, the FP32 blocks of plans that ask for it
+// run the compensated recurrence (a variant of its own: its registers would
+// otherwise spill in the FP64 kernel).
+template <bool D, bool B, bool SP = false, bool FC = false>
+__global__ __launch_bounds__(kWindowThreads) __attribute__((amdgpu_waves_per_eu(SP || FC ? 4 : (D ? 5 : 6))))
 void k_window(DevPlan P, double2 *__restrict__ m_out,
                                                            long long *__restrict__ e_out,
                                                            double2 *__restrict__ md_out,
@@ -1117,21 +1450,13 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
         const double wr = valid ? ldexp(rc.z.x, -ez) : 0.5, wi = valid ? ldexp(rc.z.y, -ez) : 0.0;
         PowState pw;                                      // chained powers of this segment
         for (int k = 0; k < kAccWords; ++k) s_acc[k][threadIdx.x] = 0;
-        // FP32 tiles: z in FP32 (|z| in [2^-12, 2^12]) and z^8 in FP64
+        // FP32 tiles: z in FP32 (|z| in [2^-12, 2^12]) and z^8, 8 z^7 in FP64
         const bool z32ok = !valid || (ez >= -11 && ez <= 12);
-        const float zr32 = (float)ldexp(wr, ez), zi32 = (float)ldexp(wi, ez);
-        double z8r = 0.0, z8i = 0.0;
-        if (!D && S.c32) {
-            FPE_NO_CONTRACT
-            double ar = ldexp(wr, ez), ai = ldexp(wi, ez);
-            for (int q = 0; q < 3; ++q) {
-                const double nr = fma(ar, ar, -(ai * ai));
-                ai = 2.0 * ar * ai;
-                ar = nr;
-            }
-            z8r = ar;
-            z8i = ai;
-        }
+        GapPowers gp;
+        const int gbits = bit_length(C - 1);
+        if constexpr (SP) gap_powers(wr, wi, ez, gbits, gp);
+        Z32 z32 = {};
+        if (!SP && S.c32) z32 = make_z32(ldexp(wr, ez), ldexp(wi, ez));
         for (;;) {
             // ---- tile (g, c): this lane's part [lo, hi] of chunk c
             const int c0 = c * C, c1 = c0 + C - 1;
@@ -1149,17 +1474,26 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 long long pe;
                 tile_power(pw, l, lo, act, c, C, wr, wi, s_ch, s_che, t, pr, pi, pe);
                 Acc<D> acc;
+                int es = 0;                       // binary exponent of a sparse tile's sum
                 const double zr = ldexp(wr, ez), zi = ldexp(wi, ez);
                 // FP32 for the common and top parts where the chunk and every
                 // active lane's |z| allow it, then the ragged bottom in FP64
-                bool f32 = false;
-                if constexpr (!D) {
+                bool f32 = SP;
+                if constexpr (SP) {
+                    sparse_tile(S, gp, gbits, Klo, Khi, lo, hi, act, acc.hr, acc.hi, es);
+                } else {
                     if (S.c32 && C == kChunk && Ahi >= Alo) {
                         const int sg = __builtin_amdgcn_readfirstlane(S.sig32[c]);
                         f32 = sg != kNoFp32 && __ballot(act && !z32ok) == 0;
                         if (f32) {
-                            run_f32(acc.hr, acc.hi, zr32, zi32, z8r, z8i, S.c32, sg, Khi, Alo,
-                                    Ahi, hi);
+                            // the compensated form sums values; a derivative
+                            // pass runs the plain FP32 blocks for Q and Q'
+                            bool comp = false;
+                            if constexpr (FC && !D) {
+                                comp = S.f32comp != 0;
+                                if (comp) run_f32<D, true>(acc, z32, S.c32, sg, Khi, Alo, Ahi, hi);
+                            }
+                            if (!comp) run_f32<D, false>(acc, z32, S.c32, sg, Khi, Alo, Ahi, hi);
                             run_steps<kBottom>(acc, zr, zi, cf, Alo - 1, Klo, lo, hi);
                         }
                     }
@@ -1175,7 +1509,7 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
                 }
                 if (act) {
                     // times z^lo = (pr + i pi) 2^(pe + lo ez)
-                    const long long E = S.coef_shift + pe + (long long)lo * ez;
+                    const long long E = S.coef_shift + pe + (long long)lo * ez + es;
                     const double qr = fma(acc.hr, pr, -acc.hi * pi);
                     const double qi = fma(acc.hr, pi, acc.hi * pr);
                     double dqr = 0.0, dqi = 0.0;
@@ -1601,8 +1935,11 @@ __global__ __launch_bounds__(256) void k_grad_z(DevPlan P, const double2 *__rest
 int g_num_cu = 0;
 // the kernels that run the (group, chunk) tiles: values, values and
 // derivatives, adjoint
-enum TileKernel { kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2, kTileBatch = 3 };
-int g_window_blocks_per_cu[4] = {0, 0, 0, 0};
+enum TileKernel {
+    kTileValue = 0, kTileDeriv = 1, kTileAdjoint = 2, kTileBatch = 3, kTileSparse = 4, kTileComp = 5, kTileBatchComp = 6,
+    kTileKinds = 7
+};
+int g_window_blocks_per_cu[kTileKinds] = {};
 int g_final_blocks_per_cu[3] = {0, 0, 0};   // k_finalize: values, derivatives, batch
 
 // wavefronts of a tile kernel: as many as are resident at once on the device
@@ -1638,17 +1975,20 @@ hipError_t prof_event(hipEvent_t *ev) {
 // compute units and resident window workgroups per compute unit (once per process)
 hipError_t device_setup() {
     if (g_num_cu > 0) return hipSuccess;
-    int dev = 0, ncu = 0, nb[4] = {0, 0, 0, 0};
+    int dev = 0, ncu = 0, nb[kTileKinds] = {};
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const void *kern[4] = {reinterpret_cast<const void *>(k_window<false, false>),
-                           reinterpret_cast<const void *>(k_window<true, false>),
-                           reinterpret_cast<const void *>(k_adjoint),
-                           reinterpret_cast<const void *>(k_window<false, true>)};
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    const void *kern[kTileKinds] = {reinterpret_cast<const void *>(k_window<false, false>),
+                                    reinterpret_cast<const void *>(k_window<true, false>),
+                                    reinterpret_cast<const void *>(k_adjoint),
+                                    reinterpret_cast<const void *>(k_window<false, true>),
+                                    reinterpret_cast<const void *>(k_window<false, false, true>),
+                                    reinterpret_cast<const void *>(k_window<false, false, false, true>),
+                                    reinterpret_cast<const void *>(k_window<false, true, false, true>)};
+    for (int i = 0; i < kTileKinds && e == hipSuccess; ++i)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb[i], kern[i], kWindowThreads, 0);
     if (e != hipSuccess) return e;
-    for (int i = 0; i < 4; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
+    for (int i = 0; i < kTileKinds; ++i) g_window_blocks_per_cu[i] = nb[i] > 0 ? nb[i] : 1;
     const void *fin[3] = {reinterpret_cast<const void *>(k_finalize<false, false>),
                           reinterpret_cast<const void *>(k_finalize<true, false>),
                           reinterpret_cast<const void *>(k_finalize<false, true>)};
@@ -1783,6 +2123,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.ghi = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcost = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gcum = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.gdens = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
     w.gblk_sum = (int32_t *)take(sizeof(int32_t) * (nblk_g > 0 ? nblk_g : 1));
     w.gblk_pre = (int32_t *)take(sizeof(int32_t) * (nblk_g > 0 ? nblk_g : 1));
     w.gseg_sum = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
@@ -1796,8 +2137,10 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.n_waves = std::min<int64_t>(w.n_waves, (int64_t)(kLongLds - 1) * kFinalShort);
     // one workspace serves every tile kernel, unless sized for this kind alone
     const int64_t nw_max = tight ? w.n_waves
-                                 : std::max(std::max(window_waves(kTileValue), window_waves(kTileDeriv)),
-                                            std::max(window_waves(kTileAdjoint), window_waves(kTileBatch)));
+                                 : std::max({window_waves(kTileValue), window_waves(kTileDeriv),
+                                             window_waves(kTileAdjoint), window_waves(kTileBatch),
+                                             window_waves(kTileSparse), window_waves(kTileComp),
+                                             window_waves(kTileBatchComp)});
     w.wstart = (int2 *)take(sizeof(int2) * (nw_max + 1));
     w.slots = (long long *)take(sizeof(long long) * kSlotWords * kWave * 2 * nw_max);
     const int64_t nlong = long_cap(nw_max);
@@ -1814,6 +2157,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.plans = nullptr;
     w.gpoly = nullptr;
     w.n_slots = batch ? nslot : -1;
+    w.sparse = kind == kTileSparse ? 1 : 0;
     if (ws) *ws = w;
     return off;
 }
@@ -1823,12 +2167,21 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
 using namespace fpe;
 
 // ---------------------------------------------------------------- tile schedule
-// The chunk length C of the (group, chunk) tiles: the one fpe_autotune chose or
-// fpe_plan_set_chunk set for this plan, else the one tuned earlier in this
-// process for the same (degree, points, FP32, batch) bucket, else kChunk.  FP32
-// plans keep kChunk (their FP32 table is scaled per kChunk coefficients).
+// The chunk length C of the (group, chunk) tiles and the form of the window
+// sums (dense: Horner's rule over every index with bad coefficients masked;
+// sparse: over the list of G_p with gaps jumped by powers of z): the ones
+// fpe_autotune chose or fpe_plan_set_chunk / fpe_plan_set_window_mode set for
+// this plan, else the ones tuned earlier in this process for the same
+// (degree, points, |G_p|, FP32, batch) bucket, else C = kChunk and the dense
+// form (the density of G_p inside the windows, which decides, is only known by
+// evaluating: the wide-range workloads hold G_p on 1/267 of the indices but on
+// 1/13 of their windows' indices, where the dense form is faster).  FP32
+// plans keep kChunk and the dense form (their FP32 table is scaled per kChunk
+// coefficients); derivatives and the reverse mode always run the dense form.
 namespace {
-std::map<std::tuple<int, int, int, int>, int> g_tuned_chunk;
+typedef std::tuple<int, int, int, int, int> TuneKey;
+struct TileChoice { int chunk; bool sparse; };
+std::map<TuneKey, TileChoice> g_tuned;
 std::mutex g_tuned_mu;
 
 int bucket(int64_t x) {
@@ -1837,23 +2190,35 @@ int bucket(int64_t x) {
     return b;
 }
 
-std::tuple<int, int, int, int> tune_key(int64_t d, int64_t n, bool fp32, bool batch) {
-    return {bucket(d), bucket(n), fp32 ? 1 : 0, batch ? 1 : 0};
+TuneKey tune_key(int64_t d, int64_t n, int64_t ngood, bool fp32, bool batch) {
+    return {bucket(d), bucket(n), bucket(ngood), fp32 ? 1 : 0, batch ? 1 : 0};
 }
 
-int cached_chunk(const std::tuple<int, int, int, int> &key) {
+bool cached_choice(const TuneKey &key, TileChoice *c) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
-    auto it = g_tuned_chunk.find(key);
-    return it == g_tuned_chunk.end() ? kChunk : it->second;
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end()) return false;
+    *c = it->second;
+    return true;
+}
+
+int cached_chunk(const TuneKey &key) {
+    TileChoice c;
+    return cached_choice(key, &c) ? c.chunk : kChunk;
 }
 
 bool valid_chunk(int c) { return c >= kChunkMin && c <= kChunkMax && (c & (c - 1)) == 0; }
 
-int plan_chunk(const fpe_plan_s *plan, int64_t n) {
-    if (plan->dev.coef32) return kChunk;
-    if (plan->chunk_sel) return plan->chunk_sel;
-    return cached_chunk(tune_key(plan->d, n, false, false));
+TileChoice plan_choice(const fpe_plan_s *plan, int64_t n) {
+    if (plan->dev.coef32) return {kChunk, false};
+    TileChoice c;
+    if (!cached_choice(tune_key(plan->d, n, plan->ngood, false, false), &c)) c = {kChunk, false};
+    if (plan->chunk_sel) c.chunk = plan->chunk_sel;
+    if (plan->mode_sel) c.sparse = plan->mode_sel == FPE_WINDOW_SPARSE;
+    return c;
 }
+
+int plan_chunk(const fpe_plan_s *plan, int64_t n) { return plan_choice(plan, n).chunk; }
 }  // namespace
 
 extern "C" fpe_status fpe_eval_workspace_size(fpe_plan_t plan, int64_t n, size_t *bytes) {
@@ -1905,9 +2270,11 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
     size_t need = 0;
     fpe_status st = fpe_eval_workspace_size(plan, n, &need);
     if (st != FPE_OK) return st;
-    if (tight)
-        need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, deriv ? kTileDeriv : kTileValue, -1,
-                                    plan_chunk(plan, n), true);
+    const TileChoice tc = plan_choice(plan, n);
+    const bool sparse = !deriv && tc.sparse;
+    const bool comp = !deriv && plan->dev.f32comp;
+    const int kind = sparse ? kTileSparse : (deriv ? kTileDeriv : (comp ? kTileComp : kTileValue));
+    if (tight) need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, kind, -1, tc.chunk, true);
     if (n == 0) { set_error(""); return FPE_OK; }
     if (!z_dev || !m_dev || !e_dev || !workspace_dev || (deriv && !ed_dev))
         return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
@@ -1917,8 +2284,7 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
         reinterpret_cast<uintptr_t>(m_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(md_dev) % 16 != 0)
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
-    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, deriv ? kTileDeriv : kTileValue, -1, plan_chunk(plan, n),
-                         tight);
+    eval_workspace_bytes(plan->dev, n, &W, workspace_dev, kind, -1, tc.chunk, tight);
     const bool prof = g_prof.on && !tight;
     const DevPlan &P = plan->dev;
     const double2 *z = reinterpret_cast<const double2 *>(z_dev);
@@ -1940,6 +2306,8 @@ static fpe_status eval_impl(fpe_plan_t plan, const double *z_dev, int64_t n, dou
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
         if (deriv) k_window<true, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, md, ed, W);
+        else if (sparse) k_window<false, false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        else if (comp) k_window<false, false, false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         else k_window<false, false><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         if (prof) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
@@ -2016,7 +2384,9 @@ extern "C" fpe_status fpe_eval_noalloc(fpe_plan_t plan, const double *z_dev, int
     FPE_HIP_CHECK(device_setup());
     if (cost_shift_for(plan->dev, n, kChunkMin) < 0)
         return fail(FPE_ERR_UNSUPPORTED, "too many (point group, chunk) tiles");
-    const size_t need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, kTileValue, -1, plan_chunk(plan, n), true);
+    const TileChoice tc = plan_choice(plan, n);
+    const size_t need = eval_workspace_bytes(plan->dev, n, nullptr, nullptr, tc.sparse ? kTileSparse : kTileValue, -1,
+                                             tc.chunk, true);
     if (need > kScratchBytes)
         return fail(FPE_ERR_WORKSPACE, "fpe_eval_noalloc: " + std::to_string(n) + " points need " +
                                            std::to_string(need) + " bytes of workspace, above the static " +
@@ -2144,6 +2514,7 @@ struct fpe_batch_s {
     int64_t max_span;              // the longest trimmed coefficient range of its plans
     int64_t mean_degree;
     bool any_fp32;
+    bool any_f32comp;              // some plan asks for compensated FP32 blocks
     int32_t chunk_sel = 0;         // chosen by fpe_batch_autotune or set; 0: cached choice or default
 };
 
@@ -2152,7 +2523,7 @@ namespace {
 int batch_chunk(const fpe_batch_s *b) {
     if (b->any_fp32) return kChunk;
     if (b->chunk_sel) return b->chunk_sel;
-    return cached_chunk(tune_key(b->mean_degree, b->n_points, false, true));
+    return cached_chunk(tune_key(b->mean_degree, b->n_points, 0, false, true));
 }
 
 struct BatchLayout { size_t plans, pstart, gstart, gpoly, total; };
@@ -2218,7 +2589,7 @@ extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, 
     std::vector<long long> ps(n_poly + 1);
     std::vector<int32_t> gs(n_poly + 1), gp((size_t)(G > 0 ? G : 1), 0);
     int64_t chunks_max = 1, span_max = 1, deg_sum = 0;
-    bool any_fp32 = false;
+    bool any_fp32 = false, any_f32comp = false;
     gs[0] = 0;
     for (int32_t i = 0; i < n_poly; ++i) {
         if (!plans[i]) return fail(FPE_ERR_INVALID_ARG, "NULL plan in the batch");
@@ -2231,6 +2602,7 @@ extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, 
         }
         deg_sum += plans[i]->d;
         any_fp32 = any_fp32 || Q.coef32 != nullptr;
+        any_f32comp = any_f32comp || Q.f32comp != 0;
         ps[i] = z_offsets[i];
         const int32_t ng = (int32_t)((z_offsets[i + 1] - z_offsets[i] + kWave - 1) / kWave);
         gs[i + 1] = gs[i] + ng;
@@ -2259,6 +2631,7 @@ extern "C" fpe_status fpe_batch_create(const fpe_plan_t *plans, int32_t n_poly, 
     bt->max_span = span_max;
     bt->mean_degree = deg_sum / n_poly;
     bt->any_fp32 = any_fp32;
+    bt->any_f32comp = any_f32comp;
     *out_batch = bt.release();
     set_error("");
     return FPE_OK;
@@ -2273,7 +2646,8 @@ extern "C" fpe_status fpe_batch_destroy(fpe_batch_t batch) {
 extern "C" fpe_status fpe_eval_batched_workspace_size(fpe_batch_t batch, size_t *bytes) {
     if (!batch || !bytes) return fail(FPE_ERR_INVALID_ARG, "NULL pointer");
     FPE_HIP_CHECK(device_setup());       // the resident wavefronts size the partition's tables
-    *bytes = eval_workspace_bytes(batch->rep, batch->n_points, nullptr, nullptr, kTileBatch, batch->n_groups);
+    *bytes = eval_workspace_bytes(batch->rep, batch->n_points, nullptr, nullptr,
+                                  batch->any_f32comp ? kTileBatchComp : kTileBatch, batch->n_groups);
     set_error("");
     return FPE_OK;
 }
@@ -2296,7 +2670,8 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
         return fail(FPE_ERR_INVALID_ARG, "misaligned buffer");
     EvalWs W;
     const int C = batch_chunk(batch);
-    eval_workspace_bytes(batch->rep, n, &W, workspace_dev, kTileBatch, batch->n_groups, C);
+    eval_workspace_bytes(batch->rep, n, &W, workspace_dev, batch->any_f32comp ? kTileBatchComp : kTileBatch,
+                         batch->n_groups, C);
     W.plans = batch->plans_dev;
     W.gpoly = batch->gpoly_dev;
     W.cost_shift = cost_shift_for_chunks(batch->n_groups, batch->max_span / C + 2, C);
@@ -2316,7 +2691,10 @@ extern "C" fpe_status fpe_eval_batched(fpe_batch_t batch, const double *z_dev, d
             FPE_HIP_CHECK(prof_event(&ev1));
             FPE_HIP_CHECK(hipEventRecord(ev0, stream));
         }
-        k_window<false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        if (batch->any_f32comp)
+            k_window<false, true, false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
+        else
+            k_window<false, true><<<wb, kWindowThreads, 0, stream>>>(P, m, e, nullptr, nullptr, W);
         if (g_prof.on) {
             FPE_HIP_CHECK(hipEventRecord(ev1, stream));
             g_prof.pending.emplace_back(ev0, ev1);
@@ -2368,27 +2746,54 @@ extern "C" fpe_status fpe_plan_set_chunk(fpe_plan_t plan, int32_t chunk) {
     return FPE_OK;
 }
 
+extern "C" fpe_status fpe_plan_set_window_mode(fpe_plan_t plan, int32_t mode) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (mode != FPE_WINDOW_AUTO && mode != FPE_WINDOW_DENSE && mode != FPE_WINDOW_SPARSE)
+        return fail(FPE_ERR_INVALID_ARG, "mode must be FPE_WINDOW_AUTO, FPE_WINDOW_DENSE or FPE_WINDOW_SPARSE");
+    if (mode == FPE_WINDOW_SPARSE && plan->dev.coef32)
+        return fail(FPE_ERR_UNSUPPORTED, "FP32 plans sum their windows in the dense form");
+    plan->mode_sel = mode;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_plan_tile_choice(fpe_plan_t plan, int64_t n, int32_t *chunk_out, int32_t *mode_out) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (n < 0) return fail(FPE_ERR_INVALID_ARG, "n out of range");
+    const TileChoice c = plan_choice(plan, n);
+    if (chunk_out) *chunk_out = c.chunk;
+    if (mode_out) *mode_out = c.sparse ? FPE_WINDOW_SPARSE : FPE_WINDOW_DENSE;
+    set_error("");
+    return FPE_OK;
+}
+
 extern "C" fpe_status fpe_autotune(fpe_plan_t plan, const double *z_dev, int64_t n, double *m_dev, int64_t *e_dev,
                                    void *workspace_dev, size_t workspace_bytes, hipStream_t stream,
                                    int32_t *chunk_out) {
     if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
     const bool fp32 = plan->dev.coef32 != nullptr;
     int best = kChunk;
+    bool best_sparse = false;
     float best_ms = -1.0f;
     if (!fp32 && n > 0) {
-        for (int C : kChunkCandidates) {
-            plan->chunk_sel = C;
-            float ms = 0.0f;
-            fpe_status st = time_calls([&] {
-                return fpe_eval(plan, z_dev, n, m_dev, e_dev, nullptr, nullptr, workspace_dev, workspace_bytes, stream);
-            }, stream, &ms);
-            if (st != FPE_OK) { plan->chunk_sel = 0; return st; }
-            if (best_ms < 0.0f || ms < best_ms) { best_ms = ms; best = C; }
+        for (int mode : {FPE_WINDOW_DENSE, FPE_WINDOW_SPARSE}) {
+            for (int C : kChunkCandidates) {
+                plan->chunk_sel = C;
+                plan->mode_sel = mode;
+                float ms = 0.0f;
+                fpe_status st = time_calls([&] {
+                    return fpe_eval(plan, z_dev, n, m_dev, e_dev, nullptr, nullptr, workspace_dev, workspace_bytes,
+                                    stream);
+                }, stream, &ms);
+                if (st != FPE_OK) { plan->chunk_sel = 0; plan->mode_sel = 0; return st; }
+                if (best_ms < 0.0f || ms < best_ms) { best_ms = ms; best = C; best_sparse = mode == FPE_WINDOW_SPARSE; }
+            }
         }
         std::lock_guard<std::mutex> lk(g_tuned_mu);
-        g_tuned_chunk[tune_key(plan->d, n, false, false)] = best;
+        g_tuned[tune_key(plan->d, n, plan->ngood, false, false)] = {best, best_sparse};
     }
     plan->chunk_sel = fp32 ? 0 : best;
+    plan->mode_sel = fp32 ? 0 : (best_sparse ? FPE_WINDOW_SPARSE : FPE_WINDOW_DENSE);
     if (chunk_out) *chunk_out = best;
     set_error("");
     return FPE_OK;
@@ -2421,7 +2826,7 @@ extern "C" fpe_status fpe_batch_autotune(fpe_batch_t batch, const double *z_dev,
             if (best_ms < 0.0f || ms < best_ms) { best_ms = ms; best = C; }
         }
         std::lock_guard<std::mutex> lk(g_tuned_mu);
-        g_tuned_chunk[tune_key(batch->mean_degree, batch->n_points, false, true)] = best;
+        g_tuned[tune_key(batch->mean_degree, batch->n_points, 0, false, true)] = {best, false};
     }
     batch->chunk_sel = batch->any_fp32 ? 0 : best;
     if (chunk_out) *chunk_out = best;

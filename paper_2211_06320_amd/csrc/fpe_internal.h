@@ -26,6 +26,8 @@ constexpr int32_t kNegInfScale = INT32_MIN;
 struct DevPlan {
     const double2 *coef;      // a_k for k in G_p, 0 elsewhere; k = 0 .. dt
     const int32_t *gprefix;   // gprefix[k] = #(G_p within [0, k)); k = 0 .. dt + 1
+    const int32_t *gidx;      // G_p as a list: its indices in increasing order (|G_p| entries)
+    const double2 *gcoef;     //   and their coefficients, as in coef
     const double *hull_k;     // cover vertices: abscissae k_i (exact in double)
     const double *hull_s;     // cover vertices: s(a_{k_i})
     int32_t nh;               // number of vertices; 0 when P == 0
@@ -41,6 +43,7 @@ struct DevPlan {
     // chunk's tiles stay in FP64
     const float2 *coef32;
     const int32_t *sig32;
+    int32_t f32comp;          // FP32 blocks by the compensated recurrence (FPE_PRECONDITION_FP32_COMPENSATED)
 };
 constexpr int32_t kNoFp32 = INT32_MIN;
 
@@ -85,6 +88,11 @@ struct EvalWs {
     const int32_t *gpoly;
     int64_t n_slots;
     int32_t chunk;                // coefficient chunk length C of the tiles (a power of two)
+    // sparse window sums (the list of G_p with gaps jumped by powers of z):
+    // per group the share of its union window's Horner steps its tiles cost,
+    // in 1/256 (256 for dense window sums)
+    int32_t sparse;
+    int32_t *gdens;
 };
 
 // tight: the per-wavefront tables sized for this kind of tile kernel alone (by
@@ -285,10 +293,10 @@ __device__ __forceinline__ int wave_max(int v) {
 struct fpe_plan_s {
     fpe::DevPlan dev;
     int64_t d, v, dt, nh, ngood, T, p, smax, smin_good;
-    std::vector<int64_t> hull_k, hull_s;
     const int32_t *good_dev = nullptr;   // d + 1 flags of G_p, in the plan's workspace
     int device;
     int32_t chunk_sel = 0;           // chunk length chosen by fpe_autotune or set; 0: cached choice or default
+    int32_t mode_sel = 0;            // window-sum form chosen or set (FPE_WINDOW_*); 0: cached choice or default
 };
 
 namespace fpe {

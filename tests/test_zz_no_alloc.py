@@ -7,6 +7,7 @@ torch's allocator sees no new memory during the calls."""
 from __future__ import annotations
 
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -50,13 +51,21 @@ def test_noalloc_matches_fpe_eval_twice(fpe):
         e = torch.full((n,), -7, dtype=torch.int64, device=dev)
         t = torch.full((n,), -1, dtype=torch.int32, device=dev)
         win = torch.full((n, 2), -1, dtype=torch.int64, device=dev)
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
-        before = torch.cuda.memory_allocated()
-        st = fpe.lib().fpe_eval_noalloc(plan._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), t.data_ptr(),
-                                        win.data_ptr(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-        assert st == fpe.FPE_OK, fpe.lib().fpe_last_error()
-        torch.cuda.synchronize()
-        assert torch.cuda.memory_allocated() == before
+        # no collection of earlier tests' tensors inside the measured region
+        gc.collect()
+        gc.disable()
+        try:
+            before = torch.cuda.memory_allocated()
+            st = fpe.lib().fpe_eval_noalloc(plan._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), t.data_ptr(),
+                                            win.data_ptr(), stream)
+            assert st == fpe.FPE_OK, fpe.lib().fpe_last_error()
+            torch.cuda.synchronize()
+            after = torch.cuda.memory_allocated()
+        finally:
+            gc.enable()
+        assert after == before
         assert torch.equal(m, m0) and torch.equal(e, e0)
         assert torch.equal(t, t0) and torch.equal(win, w0)
         # a sample against the oracle's window sum at the same precision
