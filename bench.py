@@ -65,6 +65,35 @@ def window_sources_sha256() -> str:
     return h.hexdigest()
 
 
+VALU_PROFILE = os.path.join(ROOT, "profiles", "k_window_uniform_d1e6_valu_l2.txt")
+
+
+def recorded_counters(workload: str, chunk: int):
+    """The window kernel's FP64 VALU and L2 counters per launch from the
+    committed rocprofv3 summary (executed FP64 TFLOP/s, VALU busy and
+    utilisation, L2 hit rate), or None when it is missing, for another workload
+    or chunk length, or for other kernel sources."""
+    if workload != "uniform_d1e6" or not os.path.exists(VALU_PROFILE):
+        return None
+    kv = {}
+    with open(VALU_PROFILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.split("#")[0].strip()
+    if kv.get("window_sources_sha256") != window_sources_sha256():
+        return None
+    try:
+        return {"executed_fp64_tflops": float(kv[f"executed_fp64_tflops_c{chunk}"]),
+                "executed_frac": float(kv[f"executed_fp64_tflops_c{chunk}"]) / FP64_VECTOR_PEAK_TFLOPS,
+                "valu_busy_percent": float(kv[f"valu_busy_percent_c{chunk}"]),
+                "valu_utilisation_percent": float(kv[f"valu_utilisation_percent_c{chunk}"]),
+                "l2_hit_rate": float(kv[f"l2_hit_rate_c{chunk}"]),
+                "profile": os.path.relpath(VALU_PROFILE, ROOT)}
+    except (KeyError, ValueError):
+        return None
+
+
 def recorded_traffic(workload: str, chunk: int):
     """HBM bytes per window-kernel launch from the committed counter summary, or
     None when it is missing, for another workload or chunk length, or for other
@@ -89,7 +118,8 @@ def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
     """Derivative, reverse mode and Newton at d = 2^18 with 2^20 points: the
     forward pass with Q' (fpe_eval_deriv), the backward pass of
     L = sum_j |Q_j|^2 4^(-e_j) (each point's |Q|^2 normalised by its detached
-    exponent, so that no term overflows; upstream gradient 2 Q_j 4^(-e_j)) with
+    exponent, so that no term overflows; upstream gradient 2 Q_j 4^(-e_j), passed
+    as 2 m_j with the exponent -e_j applied inside the kernels) with
     respect to every a_k and z_j (fpe_eval_adjoint), and one Newton step on
     every point (fpe_newton_step)."""
     wl = workloads.workload("uniform_d2p18")
@@ -97,7 +127,7 @@ def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
     z = torch.from_numpy(wl.points).to(dev)
     plan = fpe.precondition(c, 53)
     m, e, md, ed = plan.eval_deriv(z)
-    g = 2.0 * m * torch.pow(2.0, -e.to(torch.float64))
+    g = 2.0 * m                       # upstream gradients 2 Q_j 4^-e_j = (2 m_j) 2^-e_j
     torch.cuda.synchronize()
 
     def timed(fn):
@@ -113,18 +143,40 @@ def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
 
     n = len(wl.points)
     t_fwd = timed(lambda: plan.eval_deriv(z))
-    t_bwd = timed(lambda: plan.adjoint(z, g, md, ed))
+    t_bwd = timed(lambda: plan.adjoint(z, g, md, ed, g_exp=e))
     t_newton = timed(lambda: plan.newton_step(z))
     log(f"d=2^18, 2^20 points: forward with Q' {t_fwd:.3f} ms, backward {t_bwd:.3f} ms, Newton step {t_newton:.3f} ms")
-    return {"workload": wl.name, "d": wl.degree, "n_points": n, "unit": "points/s",
-            "forward_with_derivative": {"ms": t_fwd, "value": n / (t_fwd * 1e-3)},
-            "backward_grad_a_and_z": {"ms": t_bwd, "value": n / (t_bwd * 1e-3)},
-            "newton_step": {"ms": t_newton, "value": n / (t_newton * 1e-3)}}
+    out = {"workload": wl.name, "d": wl.degree, "n_points": n, "unit": "points/s",
+           "forward_with_derivative": {"ms": t_fwd, "value": n / (t_fwd * 1e-3)},
+           "backward_grad_a_and_z": {"ms": t_bwd, "value": n / (t_bwd * 1e-3)},
+           "newton_step": {"ms": t_newton, "value": n / (t_newton * 1e-3)}}
+    # p = 24: FP32 blocks for Q and Q' (and the Newton step), beside FP64
+    # arithmetic at the same p; errors of Q' against the oracle on a sample
+    import numpy as np
+    import oracle
+    idx = np.random.default_rng(12349).choice(n, 1000, replace=False)
+    ref = oracle.precondition(wl.coeffs, 24).eval_deriv(wl.points[idx])
+    for label, fp32 in (("fp32_p24", True), ("fp64_arith_p24", False)):
+        p24 = fpe.precondition(c, 24, fp32=fp32)
+        tf = timed(lambda: p24.eval_deriv(z))
+        tn = timed(lambda: p24.newton_step(z))
+        _, _, md24, ed24 = p24.eval_deriv(z)
+        torch.cuda.synchronize()
+        mdn, edn = md24.cpu().numpy()[idx], ed24.cpu().numpy()[idx]
+        ok = ref["ddwin_m"] > 0
+        err = oracle.scaled_error(mdn[ok], edn[ok], ref["md"][ok], ref["ed"][ok], ref["ddwin_m"][ok],
+                                  ref["ddwin_e"][ok])
+        out[label] = {"forward_with_derivative_ms": tf, "newton_step_ms": tn,
+                      "value_forward": n / (tf * 1e-3), "max_scaled_err_derivative": float(err.max())}
+        log(f"  {label}: forward with Q' {tf:.3f} ms, Newton step {tn:.3f} ms, Q' max scaled error {err.max():.2e}")
+    return out
 
 
 def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> dict:
-    """FP32 window sums at p = 24 (FPE_PRECONDITION_FP32) beside FP64 arithmetic at
-    the same p, on the headline workload and the two wide-range workloads
+    """FP32 window sums at p = 24 (FPE_PRECONDITION_FP32: plain FP32 blocks of 8
+    with FP64 accumulation, and with FPE_PRECONDITION_FP32_COMPENSATED the
+    blocks by the compensated TwoSum/TwoProd recurrence) beside FP64 arithmetic
+    at the same p, on the headline workload and the two wide-range workloads
     (d = 2^20): evaluations/s over all points and the max scaled error against
     the oracle at p = 24 on a seeded sample."""
     out = {}
@@ -136,8 +188,9 @@ def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> 
         idx = np.random.default_rng(12346).choice(n, min(check, n), replace=False)
         ref = oracle.precondition(wl.coeffs, 24).eval(wl.points[idx])
         row = {"d": wl.degree, "n_points": n}
-        for label, fp32 in (("fp32", True), ("fp64_arith", False)):
-            plan = fpe.precondition(c, 24, fp32=fp32)
+        for label, fp32, comp in (("fp32", True, False), ("fp32_compensated", True, True),
+                                  ("fp64_arith", False, False)):
+            plan = fpe.precondition(c, 24, fp32=fp32, compensated=comp)
             mo = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
             plan.eval(z, out=mo)
             torch.cuda.synchronize()
@@ -152,6 +205,8 @@ def fp32_leg(fpe, workloads, oracle, np, torch, dev, steps: int, check: int) -> 
             err = oracle.scaled_error(mm[idx], ee[idx], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
             row[label] = {"ms": ms, "value": n / (ms * 1e-3), "max_scaled_err": float(err.max())}
         log(f"p=24 {name}: FP32 {row['fp32']['ms']:.3f} ms (max err {row['fp32']['max_scaled_err']:.2e}), "
+            f"FP32 compensated {row['fp32_compensated']['ms']:.3f} ms "
+            f"(max err {row['fp32_compensated']['max_scaled_err']:.2e}), "
             f"FP64 arithmetic {row['fp64_arith']['ms']:.3f} ms (max err {row['fp64_arith']['max_scaled_err']:.2e})")
         out[name] = row
     out["unit"] = "evaluations/s"
@@ -322,6 +377,27 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
         sl = slice(offs[i], offs[i + 1])
         worst = max(worst, float(oracle.scaled_error(mm[sl], ee[sl], ref["m"], ref["e"], ref["dwin_m"],
                                                      ref["dwin_e"]).max()))
+    # the same batch with FP32 plans at p = 24 (plain and compensated blocks)
+    # beside FP64 arithmetic at p = 24
+    fp32_rows = {}
+    for label, fp32, comp in (("fp32_p24", True, False), ("fp32_compensated_p24", True, True),
+                              ("fp64_arith_p24", False, False)):
+        pl24 = fpe.precondition_batched(cdev, 24, fp32=fp32, compensated=comp)
+        b24 = fpe.Batch(pl24, offs)
+        o24 = (torch.empty(n, dtype=torch.complex128, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+        b24.eval(z, out=o24)
+        torch.cuda.synchronize()
+        ms24 = timed(lambda: b24.eval(z, out=o24), steps)
+        m24, e24 = o24[0].cpu().numpy(), o24[1].cpu().numpy()
+        w24 = 0.0
+        for i in np.random.default_rng(12350).choice(len(coeffs), 8, replace=False):
+            ref = oracle.precondition(coeffs[i], 24).eval(points[i])
+            sl = slice(offs[i], offs[i + 1])
+            w24 = max(w24, float(oracle.scaled_error(m24[sl], e24[sl], ref["m"], ref["e"], ref["dwin_m"],
+                                                     ref["dwin_e"]).max()))
+        fp32_rows[label] = {"ms": ms24, "value": n / (ms24 * 1e-3), "max_scaled_err_8_polys": w24}
+        log(f"  batch {label}: {ms24:.3f} ms, max scaled error (8 polynomials) {w24:.2e}")
+        del b24, pl24
     log(f"batch of {len(plans)} polynomials, {n} points: eager {eager_ms:.3f} ms, graph replay {graph_ms:.3f} ms, "
         f"per-polynomial loop {loop_ms:.1f} ms (chunk {chunk}); preconditioning {pre_ms:.1f} ms batched, "
         f"{pre_loop_ms:.0f} ms one at a time; "
@@ -334,6 +410,7 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
             "per_polynomial_loop": {"ms": loop_ms, "value": n / (loop_ms * 1e-3)},
             "precondition_ms": pre_ms, "precondition_one_at_a_time_ms": pre_loop_ms,
             "max_scaled_err_16_polys": worst,
+            "p24": fp32_rows,
             "kept_terms": kept, "window_kernel_ms": win_ms,
             "window_tflops_kept_terms": 8 * kept / (win_ms * 1e-3) / 1e12}
 
@@ -463,7 +540,10 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "k_window", "kernel_ms": win_avg_ms,
-                     "algorithmic_flops": flops, "kept_terms": int(terms_np.sum())},
+                     "algorithmic_flops": flops, "kept_terms": int(terms_np.sum()),
+                     "hbm_gbs": traffic / (win_avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "counters": recorded_counters(wl.name, chunk),
+                     "step_frac": flops / (ms_per_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
         "precondition_ms": pre_ms,
         "mean_terms": float(terms_np.mean()),
     }

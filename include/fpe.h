@@ -21,9 +21,16 @@
  *   - Every call returns an fpe_status; FPE_OK is 0.  Nothing is printed and no
  *     exception crosses the ABI.  fpe_last_error() gives a thread-local detail
  *     string for the last failing call on the calling thread.
- *   - Work is enqueued on the given stream.  Only fpe_precondition waits for
- *     the stream (it builds the concave cover on the host); fpe_eval and
- *     fpe_horner_eval only enqueue and return.
+ *   - Work is enqueued on the given stream.  These calls wait for it before
+ *     returning (they read counters back to the host to build a host handle or
+ *     to time): fpe_precondition, fpe_precondition_batched, fpe_cover_build,
+ *     fpe_plan_from_cover, fpe_batch_create, fpe_autotune,
+ *     fpe_batch_autotune and fpe_profile_read; fpe_plan_export copies from the
+ *     device synchronously.  Every other call (fpe_eval, fpe_eval_noalloc,
+ *     fpe_eval_deriv, fpe_newton_step, fpe_eval_adjoint, fpe_cancelled_bits,
+ *     fpe_eval_batched, fpe_horner_eval) only enqueues kernels and returns, so
+ *     a HIP graph can capture it once a first call has set the library up on
+ *     the device (occupancy queries).
  */
 #ifndef FPE_H
 #define FPE_H
@@ -325,6 +332,10 @@ fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n,
  *
  *   z_dev, n         as fpe_eval.
  *   g_dev            2n doubles: the upstream gradients, input order.
+ *   g_exp_dev        NULL, or n int64: the upstream gradients are then
+ *                    g_j 2^(-g_exp[j]) (the exponent applied inside, so that a
+ *                    gradient with respect to a normalised value m_j = Q_j 2^-e_j
+ *                    passes with g_exp = e and nothing underflows).
  *   md_dev, ed_dev   Q' = md 2^ed from fpe_eval_deriv at the same points (only
  *                    read when grad_z_dev is not NULL).
  *   grad_a_dev       output, or NULL to skip: 2 (d + 1) doubles, overwritten
@@ -340,8 +351,8 @@ fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n,
  * a_0 != 0.  grad_a sums the points' terms with FP64 atomic additions, so its
  * last bits can vary from call to call.  Errors as fpe_eval. */
 fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, const double *g_dev,
-                            const double *md_dev, const int64_t *ed_dev, double *grad_a_dev,
-                            double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
+                            const int64_t *g_exp_dev, const double *md_dev, const int64_t *ed_dev,
+                            double *grad_a_dev, double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */

@@ -14,6 +14,7 @@ There is no fallback: if libfpe.so is missing, loading fails with an error.
     m, e, md, ed = plan.eval_deriv(z)      # and Q' = md * 2**ed through the same window
     ga, gz = plan.adjoint(z, g)            # reverse mode for upstream gradients g
     q = fpe_eval(coeffs, z)                # differentiable (torch.autograd)
+    q, e = eval_scaled(plan, coeffs, z)    # differentiable normalised values, Q = q 2^e
     cov = Cover(coeffs); p53, p24 = cov.plan(53), cov.plan(24)    # the cover once, G_p per precision
     plans = precondition_batched([c1, c2, c3])                      # many polynomials, one launch sequence
     b = Batch([plan_a, plan_b], [0, na, na + nb]); m, e = b.eval(z_ab)   # many polynomials at once
@@ -126,7 +127,7 @@ def lib() -> ctypes.CDLL:
     L.fpe_batch_autotune.restype = i32
     L.fpe_batch_autotune.argtypes = [vp, vp, vp, vp, vp, sz, vp, P(i32)]
     L.fpe_eval_adjoint.restype = i32
-    L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fpe_eval_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fpe_cancelled_bits.restype = i32
     L.fpe_cancelled_bits.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.fpe_horner_eval.restype = i32
@@ -374,19 +375,24 @@ class Plan:
                                         bits.data_ptr(), _stream(stream)))
         return bits
 
-    def adjoint(self, z, g, md=None, ed=None, grad_a: bool = True, grad_z: bool = True, stream=None):
+    def adjoint(self, z, g, md=None, ed=None, grad_a: bool = True, grad_z: bool = True, g_exp=None, stream=None):
         """Reverse mode of Q_lambda for upstream gradients g (complex convention:
         upstream gradient times the conjugate derivative; the kept terms held
         fixed).  Returns (grad_a [d + 1] or None, grad_z [n] or None):
         grad_a[k] = sum of g_j conj(z_j)^k over the points keeping k,
         grad_z[j] = g_j conj(Q'(z_j)), Q' = md 2^ed from eval_deriv (computed
-        here when not given)."""
+        here when not given).  g_exp (int64 [n], optional): the upstream
+        gradients are g_j 2^(-g_exp[j])."""
         torch = _torch()
         z = _dev_complex(z, "z")
         g = _dev_complex(g, "g")
         n = z.shape[0]
         if g.shape != z.shape:
             raise ValueError("g must have the shape of z")
+        if g_exp is not None:
+            if g_exp.shape != z.shape or g_exp.dtype != torch.int64 or g_exp.device != z.device:
+                raise ValueError("g_exp must be an int64 tensor shaped like z on its device")
+            g_exp = g_exp.contiguous()
         if grad_z and (md is None or ed is None):
             _, _, md, ed = self.eval_deriv(z, stream=stream)
         ga = torch.empty(self.d + 1, dtype=torch.complex128, device=z.device) if grad_a else None
@@ -396,6 +402,7 @@ class Plan:
             ed = ed.contiguous()
         ws, nb = self.workspace(n)
         _check(lib().fpe_eval_adjoint(self._h, z.data_ptr(), n, g.data_ptr(),
+                                      g_exp.data_ptr() if g_exp is not None else None,
                                       md.data_ptr() if grad_z else None, ed.data_ptr() if grad_z else None,
                                       ga.data_ptr() if ga is not None else None,
                                       gz.data_ptr() if gz is not None else None, ws, nb, _stream(stream)))
@@ -503,7 +510,44 @@ def _fpe_function():
     return FPEEval
 
 
+def _fpe_scaled_function():
+    torch = _torch()
+
+    class FPEEvalScaled(torch.autograd.Function):
+        """Q_lambda(z) = q 2^e per point for a prebuilt plan of the coefficients a:
+        q complex128 (normalised mantissas, differentiable) and e int64 (the
+        binary exponents, treated as constants).  The backward pass is
+        fpe_eval_adjoint with the upstream gradient of q passed as g 2^-e, so a
+        loss on the normalised values (say sum |q_j|^2 = sum |Q_j|^2 4^-e_j)
+        backpropagates without any value leaving the double range.  The plan
+        must have been preconditioned from a (its kept set is held fixed)."""
+
+        @staticmethod
+        def forward(ctx, coeffs, z, plan):
+            zd = z.detach()
+            if ctx.needs_input_grad[1]:
+                m, e, md, ed = plan.eval_deriv(zd)
+            else:
+                m, e = plan.eval(zd)
+                md = ed = None
+            ctx.plan = plan
+            ctx.z, ctx.e, ctx.md, ctx.ed = zd, e, md, ed
+            ctx.mark_non_differentiable(e)
+            return m, e
+
+        @staticmethod
+        def backward(ctx, gq, ge):
+            if gq is None:
+                return None, None, None
+            ga, gz = ctx.plan.adjoint(ctx.z, gq.contiguous(), ctx.md, ctx.ed, grad_a=ctx.needs_input_grad[0],
+                                      grad_z=ctx.needs_input_grad[1], g_exp=ctx.e)
+            return ga, gz, None
+
+    return FPEEvalScaled
+
+
 _FPE_FN = None
+_FPE_SCALED_FN = None
 
 
 def fpe_eval(coeffs, z, p: int = 53):
@@ -512,6 +556,16 @@ def fpe_eval(coeffs, z, p: int = 53):
     if _FPE_FN is None:
         _FPE_FN = _fpe_function()
     return _FPE_FN.apply(_dev_complex(coeffs, "coeffs"), _dev_complex(z, "z"), p)
+
+
+def eval_scaled(plan, coeffs, z):
+    """Differentiable (q, e) with Q_lambda(z_j) = q_j 2^(e_j) for a prebuilt plan
+    of coeffs: q complex128 [n] differentiable in coeffs and z, e int64 [n]
+    constant.  Losses on q stay in range where |Q| itself leaves the double range."""
+    global _FPE_SCALED_FN
+    if _FPE_SCALED_FN is None:
+        _FPE_SCALED_FN = _fpe_scaled_function()
+    return _FPE_SCALED_FN.apply(_dev_complex(coeffs, "coeffs"), _dev_complex(z, "z"), plan)
 
 
 class Cover:

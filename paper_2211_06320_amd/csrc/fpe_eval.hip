@@ -1775,6 +1775,7 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
 constexpr int kRenormSteps = 256;   // products by conj(w) between two folds of the term mantissa
 
 __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const double2 *__restrict__ gin,
+                                                            const long long *__restrict__ gexp,
                                                             double2 *__restrict__ grad_a, EvalWs W) {
     const int lane = threadIdx.x % kWave;
     const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
@@ -1813,6 +1814,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
             const double gm = fmax(fabs(gj.x), fabs(gj.y));
             if (gm != 0.0 && isfinite(gm)) { eg = exp_of(gm); gr = ldexp(gj.x, -eg); gi = ldexp(gj.y, -eg); }
             else { gr = gj.x; gi = gj.y; }
+            // upstream gradients given as g 2^-gexp: the exponent joins E below
+            if (gexp) {
+                long long x = (long long)eg - gexp[rc.j];
+                eg = (int)(x < -1000000000LL ? -1000000000LL : (x > 1000000000LL ? 1000000000LL : x));
+            }
         }
         PowState pw;
         for (;;) {
@@ -1910,25 +1916,28 @@ __global__ __launch_bounds__(256) void k_zero2(double2 *__restrict__ x, int64_t 
 // (NaN for a non-finite z), and the contribution of z = 0 to a_0: there the
 // kept terms are a_0 alone (when a_0 != 0), so grad_a[0] += gin.
 __global__ __launch_bounds__(256) void k_grad_z(DevPlan P, const double2 *__restrict__ z, int n,
-                                                const double2 *__restrict__ gin, const double2 *__restrict__ md,
-                                                const long long *__restrict__ ed, double2 *__restrict__ grad_z,
-                                                double2 *__restrict__ grad_a) {
+                                                const double2 *__restrict__ gin, const long long *__restrict__ gexp,
+                                                const double2 *__restrict__ md, const long long *__restrict__ ed,
+                                                double2 *__restrict__ grad_z, double2 *__restrict__ grad_a) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
-    const double2 zz = z[j], g = gin[j];
+    const double2 zz = z[j];
+    double2 g = gin[j];
+    const long long gx = gexp ? gexp[j] : 0;
     if (grad_z) {
         if (!isfinite(zz.x) || !isfinite(zz.y)) {
             grad_z[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
         } else {
             const double2 b = md[j];
-            long long sh = ed[j];
+            long long sh = ed[j] - gx;
             sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
             grad_z[j] = make_double2(ldexp(fma(g.x, b.x, g.y * b.y), (int)sh), ldexp(fma(g.y, b.x, -g.x * b.y), (int)sh));
         }
     }
     if (grad_a && zz.x == 0.0 && zz.y == 0.0 && P.nh > 0 && P.v == 0) {
-        atomicAdd(&grad_a[0].x, g.x);
-        atomicAdd(&grad_a[0].y, g.y);
+        const int sh = (int)(gx > 2200 ? 2200 : (gx < -2200 ? -2200 : gx));
+        atomicAdd(&grad_a[0].x, ldexp(g.x, -sh));
+        atomicAdd(&grad_a[0].y, ldexp(g.y, -sh));
     }
 }
 
@@ -2458,7 +2467,8 @@ extern "C" fpe_status fpe_cancelled_bits(fpe_plan_t plan, const double *z_dev, i
 }
 
 extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, const double *g_dev,
-                                       const double *md_dev, const int64_t *ed_dev, double *grad_a_dev,
+                                       const int64_t *g_exp_dev, const double *md_dev, const int64_t *ed_dev,
+                                       double *grad_a_dev,
                                        double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
                                        hipStream_t stream) {
     if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
@@ -2488,11 +2498,12 @@ extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int
             FPE_HIP_CHECK(launch_front(P, z, ni, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, stream));
             if (P.nh > 0)
                 k_adjoint<<<(unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves), kWindowThreads, 0, stream>>>(
-                    P, g, ga, W);
+                    P, g, reinterpret_cast<const long long *>(g_exp_dev), ga, W);
         }
         if (ga || grad_z_dev)
             k_grad_z<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
-                P, z, ni, g, reinterpret_cast<const double2 *>(md_dev), reinterpret_cast<const long long *>(ed_dev),
+                P, z, ni, g, reinterpret_cast<const long long *>(g_exp_dev), reinterpret_cast<const double2 *>(md_dev),
+                reinterpret_cast<const long long *>(ed_dev),
                 reinterpret_cast<double2 *>(grad_z_dev), ga);
     }
     FPE_HIP_CHECK(hipGetLastError());

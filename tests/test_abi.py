@@ -58,6 +58,6 @@ def test_null_arguments_rejected_without_gpu_work():
     assert L.fpe_precondition(None, 10, 53, 0, None, 0, None, ctypes.byref(h)) == 1
     assert L.fpe_eval(None, None, 0, None, None, None, None, None, 0, None) == 1
     assert L.fpe_horner_eval(None, -1, None, 0, None, None, None) == 1
-    assert L.fpe_eval_adjoint(None, None, 0, None, None, None, None, None, None, 0, None) == 1
+    assert L.fpe_eval_adjoint(None, None, 0, None, None, None, None, None, None, None, 0, None) == 1
     assert L.fpe_plan_info(None, None) == 1
     assert L.fpe_plan_destroy(None) == 0

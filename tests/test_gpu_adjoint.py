@@ -302,3 +302,130 @@ def test_autograd_central_differences_restricted_windows(fpe):
         assert abs(fd - gz[j]) <= 1e-6 * abs(gz[j]) + 1e-8 / abs(zs[j]), (j, fd, gz[j])
         checked += 1
     assert checked >= 16
+
+
+# ---------------------------------------------------------------- normalised values through autograd
+def test_adjoint_exponent_scaled_gradients(fpe):
+    """g_exp: the reverse mode with upstream gradients g 2^-g_exp equals the one
+    with the scaled gradients passed directly (where those are representable),
+    to rounding."""
+    c = workloads.uniform_coeffs(3000, 91)
+    z = workloads.spherical_points(2000, 92)
+    plan = fpe.precondition(to_dev(c), 53)
+    zd = to_dev(z)
+    m, e, md, ed = plan.eval_deriv(zd)
+    ok = (e.abs() < 900)
+    g = (2.0 * m)[ok].contiguous()
+    ga1, gz1 = plan.adjoint(zd[ok].contiguous(), g, md[ok].contiguous(), ed[ok].contiguous(), g_exp=e[ok].contiguous())
+    gs = g * torch.pow(2.0, -e[ok].to(torch.float64))
+    ga2, gz2 = plan.adjoint(zd[ok].contiguous(), gs.contiguous(), md[ok].contiguous(), ed[ok].contiguous())
+    torch.cuda.synchronize()
+    sa = ga2.abs().max().item()
+    assert (ga1 - ga2).abs().max().item() <= 1e-12 * sa
+    assert ((gz1 - gz2).abs() <= 1e-12 * gz2.abs() + 1e-300).all()
+
+
+def test_autograd_normalised_values_adjoint_workload(fpe):
+    """d = 2^18 (the reverse-mode workload's polynomial), a seeded sample of its
+    2^20 spherical points, many with |Q| beyond the double range: the loss
+    L = sum_j |q_j|^2 on the normalised values Q_j = q_j 2^(e_j) (e constant)
+    backpropagates through eval_scaled to finite gradients, which agree with
+    central differences of the GPU evaluation in Re and Im of kept
+    coefficients (G_p and the cover unchanged by the step) and of points (their
+    windows unchanged)."""
+    wl = workloads.workload("uniform_d2p18")
+    rng = np.random.default_rng(93)
+    idx = rng.choice(len(wl.points), 2048, replace=False)
+    zs = wl.points[idx]
+    a = wl.coeffs
+    plan = fpe.precondition(to_dev(a), 53)
+    at = to_dev(a).requires_grad_(True)
+    zt = to_dev(zs).requires_grad_(True)
+    q, e = fpe.eval_scaled(plan, at, zt)
+    e0 = e.cpu().numpy()
+    say(f"  {int((np.abs(e0) > 1023).sum())} of {len(zs)} points have |Q| beyond the double range")
+    assert (np.abs(e0) > 1023).sum() > 100
+    L = (q.real ** 2 + q.imag ** 2).sum()
+    L.backward()
+    ga, gz = at.grad.cpu().numpy(), zt.grad.cpu().numpy()
+    assert np.isfinite(ga).all() and np.isfinite(gz).all()
+
+    def loss_np(av, zv, pl=None):
+        pl = pl or fpe.precondition(to_dev(av), 53)
+        m, ee = pl.eval(to_dev(zv))
+        m, ee = m.cpu().numpy(), ee.cpu().numpy()
+        return float(np.sum(np.abs(m) ** 2 * np.exp2(2.0 * (ee - e0))))
+
+    hk, hs, good = plan.export()
+    kept = np.flatnonzero(np.abs(ga) > 0)
+    top = kept[np.argsort(-np.abs(ga[kept]))[:200]]
+    checked = 0
+    for k in rng.choice(top, 10, replace=False):
+        h = 2.0 ** -12 * abs(a[k])
+        vals = []
+        for step in (h, -h, 1j * h, -1j * h):
+            ap = a.copy()
+            ap[k] += step
+            p2 = fpe.precondition(to_dev(ap), 53)
+            hk2, hs2, good2 = p2.export()
+            if not (np.array_equal(good2, good) and np.array_equal(hk2, hk) and np.array_equal(hs2, hs)):
+                break
+            vals.append(loss_np(ap, zs, p2))
+        if len(vals) < 4:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+        assert abs(fd - ga[k]) <= 1e-7 * abs(ga[k]) + 1e-9 / h, (k, fd, ga[k])
+        checked += 1
+    assert checked >= 6
+    # point gradients by central differences of the one point's term
+    # L_j = |Q_j|^2 2^(-2 e_j) (the other terms do not move).  The step is
+    # h = t |z| / r with t = 1e-5 for the window [l, r]: truncation ~ t^2 / 6
+    # and rounding ~ eps / t relative to the derivative scale
+    # B_j = 2 |q_j| 2^(-e_j) (sum |k a_k| |z|^(k-1) + r sum |a_k| |z|^k / |z|)
+    qn = q.detach().cpu().numpy()
+    sample = rng.choice(len(zs), 24, replace=False)
+    ref = oracle.precondition(a, 53).eval_deriv(zs[sample])
+    checked, sharp = 0, 0
+    for i, j in enumerate(sample):
+        _, _, _, w0 = plan.eval(to_dev(zs[j:j + 1]), window=True)
+        w0 = w0.cpu().numpy()[0]
+        if w0[1] < w0[0]:
+            continue
+        r = max(int(w0[1]), 1)
+        h = 1e-5 * abs(zs[j]) / r
+        vals, same = [], True
+        for step in (h, -h, 1j * h, -1j * h):
+            m, ee, _, wp = plan.eval(to_dev(np.array([zs[j] + step])), window=True)
+            same &= bool(np.array_equal(wp.cpu().numpy()[0], w0))
+            vals.append(float(abs(m.cpu().numpy()[0]) ** 2 * np.exp2(2.0 * (float(ee.cpu().numpy()[0]) - e0[j]))))
+        if not same:
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
+        dscale = ref["ddwin_m"][i] * np.exp2(float(ref["ddwin_e"][i] - e0[j]))
+        vscale = r * ref["dwin_m"][i] * np.exp2(float(ref["dwin_e"][i] - e0[j])) / abs(zs[j])
+        bound = 2.0 * abs(qn[j]) * (dscale + vscale)
+        assert abs(fd - gz[j]) <= 1e-6 * bound, (j, fd, gz[j], bound)
+        checked += 1
+        sharp += abs(gz[j]) >= 1e-2 * bound
+    assert checked >= 16 and sharp >= 8, (checked, sharp)
+    say(f"  checked {checked} points by central differences")
+
+
+def test_autograd_normalised_values_full_size(fpe):
+    """All 2^20 points of the reverse-mode workload through eval_scaled and
+    backward: finite gradients, equal to the direct reverse-mode call with
+    g = 2 q, g_exp = e (atomics add in another order: within 2^-40 of the
+    largest |grad_a| entry)."""
+    wl = workloads.workload("uniform_d2p18")
+    plan = fpe.precondition(to_dev(wl.coeffs), 53)
+    at = to_dev(wl.coeffs).requires_grad_(True)
+    zt = to_dev(wl.points).requires_grad_(True)
+    q, e = fpe.eval_scaled(plan, at, zt)
+    (q.real ** 2 + q.imag ** 2).sum().backward()
+    ga, gz = at.grad, zt.grad
+    m, e2, md, ed = plan.eval_deriv(to_dev(wl.points))
+    ga2, gz2 = plan.adjoint(to_dev(wl.points), 2.0 * m, md, ed, g_exp=e2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(ga).all() and torch.isfinite(gz).all()
+    assert (ga - ga2).abs().max().item() <= 2.0 ** -40 * ga2.abs().max().item()
+    assert torch.equal(gz, gz2)
