@@ -116,7 +116,8 @@ def recorded_traffic(workload: str, chunk: int):
 
 def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
     """Derivative, reverse mode and Newton at d = 2^18 with 2^20 points: the
-    forward pass with Q' (fpe_eval_deriv), the backward pass of
+    forward pass with Q' (fpe_eval_deriv), the backward pass (grad_a summed
+    exactly in fixed point, and with FP64 atomics) of
     L = sum_j |Q_j|^2 4^(-e_j) (each point's |Q|^2 normalised by its detached
     exponent, so that no term overflows; upstream gradient 2 Q_j 4^(-e_j), passed
     as 2 m_j with the exponent -e_j applied inside the kernels) with
@@ -144,11 +145,17 @@ def adjoint_leg(fpe, workloads, torch, dev, steps: int) -> dict:
     n = len(wl.points)
     t_fwd = timed(lambda: plan.eval_deriv(z))
     t_bwd = timed(lambda: plan.adjoint(z, g, md, ed, g_exp=e))
+    plan.set_adjoint_mode("atomic")
+    t_bwd_atomic = timed(lambda: plan.adjoint(z, g, md, ed, g_exp=e))
+    plan.set_adjoint_mode("exact")
     t_newton = timed(lambda: plan.newton_step(z))
-    log(f"d=2^18, 2^20 points: forward with Q' {t_fwd:.3f} ms, backward {t_bwd:.3f} ms, Newton step {t_newton:.3f} ms")
+    log(f"d=2^18, 2^20 points: forward with Q' {t_fwd:.3f} ms, backward {t_bwd:.3f} ms (exact sums; "
+        f"{t_bwd_atomic:.3f} ms with FP64 atomics), Newton step {t_newton:.3f} ms")
     out = {"workload": wl.name, "d": wl.degree, "n_points": n, "unit": "points/s",
            "forward_with_derivative": {"ms": t_fwd, "value": n / (t_fwd * 1e-3)},
-           "backward_grad_a_and_z": {"ms": t_bwd, "value": n / (t_bwd * 1e-3)},
+           "backward_grad_a_and_z": {"ms": t_bwd, "value": n / (t_bwd * 1e-3), "grad_a_sums": "exact"},
+           "backward_grad_a_and_z_atomic": {"ms": t_bwd_atomic, "value": n / (t_bwd_atomic * 1e-3),
+                                            "grad_a_sums": "FP64 atomics"},
            "newton_step": {"ms": t_newton, "value": n / (t_newton * 1e-3)}}
     # p = 24: FP32 blocks for Q and Q' (and the Newton step), beside FP64
     # arithmetic at the same p; errors of Q' against the oracle on a sample

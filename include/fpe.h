@@ -348,12 +348,28 @@ fpe_status fpe_newton_step(fpe_plan_t plan, const double *z_dev, int64_t n,
  * to an infinity (or NaN where an infinity meets a zero), and one below it
  * flushes to zero.  A point with a non-finite coordinate contributes nothing
  * to grad_a and gets a NaN grad_z; z = 0 contributes g_j to grad_a[0] when
- * a_0 != 0.  grad_a sums the points' terms with FP64 atomic additions, so its
- * last bits can vary from call to call.  Errors as fpe_eval. */
+ * a_0 != 0.
+ *
+ * Summation of grad_a (fpe_plan_set_adjoint_mode): by default
+ * (FPE_ADJOINT_EXACT) every term goes to fixed point relative to a per-index
+ * scale 2^E_k (E_k bounds every term at k, from a first pass over the tiles)
+ * and the terms are summed exactly with integer atomics, so grad_a has the
+ * same bits from call to call and for any order of the points; each term is
+ * rounded to 2^(E_k - 2S), S = min(47, 62 - bitlen(n)), before the exact sum,
+ * and the sum to double once.  A non-finite term makes its grad_a entry NaN.
+ * With FPE_ADJOINT_ATOMIC the wavefronts' partial sums go to grad_a with FP64
+ * atomic additions instead (one pass, about a third of the time at 2^20
+ * points; the last bits then vary from call to call).  Errors as fpe_eval. */
 fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int64_t n, const double *g_dev,
                             const int64_t *g_exp_dev, const double *md_dev, const int64_t *ed_dev,
                             double *grad_a_dev, double *grad_z_dev, void *workspace_dev, size_t workspace_bytes,
                             hipStream_t stream);
+
+/* How fpe_eval_adjoint sums grad_a on this plan (see above):
+ * FPE_ADJOINT_EXACT (the default) or FPE_ADJOINT_ATOMIC.  Errors:
+ * FPE_ERR_INVALID_ARG (NULL plan, unknown mode). */
+enum { FPE_ADJOINT_EXACT = 0, FPE_ADJOINT_ATOMIC = 1 };
+fpe_status fpe_plan_set_adjoint_mode(fpe_plan_t plan, int32_t mode);
 
 /* ------------------------------------------------------------------------- */
 /* Many polynomials in one evaluation (Algorithm A_p, second block, applied  */

@@ -34,6 +34,7 @@ FPE_OK = 0
 PRECONDITION_FP32 = 1
 PRECONDITION_FP32_COMPENSATED = 2
 WINDOW_AUTO, WINDOW_DENSE, WINDOW_SPARSE = 0, 1, 2
+ADJOINT_EXACT, ADJOINT_ATOMIC = 0, 1
 STATUS = {0: "FPE_OK", 1: "FPE_ERR_INVALID_ARG", 2: "FPE_ERR_NONFINITE", 3: "FPE_ERR_PRECISION",
           4: "FPE_ERR_WORKSPACE", 5: "FPE_ERR_HIP", 6: "FPE_ERR_UNSUPPORTED"}
 
@@ -118,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.fpe_plan_set_chunk.argtypes = [vp, i32]
     L.fpe_plan_set_window_mode.restype = i32
     L.fpe_plan_set_window_mode.argtypes = [vp, i32]
+    L.fpe_plan_set_adjoint_mode.restype = i32
+    L.fpe_plan_set_adjoint_mode.argtypes = [vp, i32]
     L.fpe_plan_tile_choice.restype = i32
     L.fpe_plan_tile_choice.argtypes = [vp, i64, P(i32), P(i32)]
     L.fpe_autotune.restype = i32
@@ -306,6 +309,12 @@ class Plan:
         (or WINDOW_AUTO / WINDOW_DENSE / WINDOW_SPARSE)."""
         m = {"auto": WINDOW_AUTO, "dense": WINDOW_DENSE, "sparse": WINDOW_SPARSE}.get(mode, mode)
         _check(lib().fpe_plan_set_window_mode(self._h, int(m)))
+
+    def set_adjoint_mode(self, mode) -> None:
+        """How adjoint sums grad_a: "exact" (fixed point, the same bits every
+        call; the default) or "atomic" (FP64 atomics, faster)."""
+        m = {"exact": ADJOINT_EXACT, "atomic": ADJOINT_ATOMIC}.get(mode, mode)
+        _check(lib().fpe_plan_set_adjoint_mode(self._h, int(m)))
 
     def tile_choice(self, n: int):
         """(chunk length, "dense" or "sparse") an evaluation of n points would use."""

@@ -35,4 +35,4 @@ extern "C" const char *fpe_status_string(fpe_status s) {
 
 extern "C" const char *fpe_last_error(void) { return fpe::t_last_error.c_str(); }
 
-extern "C" int32_t fpe_abi_version(void) { return 2; }
+extern "C" int32_t fpe_abi_version(void) { return 3; }

@@ -1770,13 +1770,124 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
 // (z^lo by tile_power) and multiplies by conj(z) per step, mantissa and
 // exponent apart, so that a term is rounded to the double range only when it
 // is emitted; the 64 lanes' terms of four consecutive k at a time are summed
-// across the wavefront by a reduce-scatter and added to grad_a[k] (FP64
-// atomics: the order of the additions, hence the last bits, can vary).
+// across the wavefront by a reduce-scatter (a fixed order).
+//
+// The sums over wavefronts are exact, so grad_a does not depend on the order
+// in which tiles finish.  Two passes over the tiles: with BOUND, each term's
+// magnitude is bounded from above, |gin conj(z)^k| < 2^(e + 1 + k lambda),
+// lambda = log2|z| and e the exponent of gin (no products, no powering), and
+// per k the largest bound, plus two, goes to aexp[k] (integer atomicMax).
+// Then every term goes to fixed point relative to 2^aexp[k]: v 2^(S -
+// aexp[k]) split into an integer part and S fraction bits, two int64 words per
+// component, summed over the wavefront and added with integer atomics, all
+// exact: grad_a depends neither on the order of the additions nor on which
+// points share a wavefront.  A term stays below 2^(S - 2) in these units and
+// an index gathers at most n terms, so S = min(47, 62 - bitlen(n)) keeps every
+// word below 2^62 and a wavefront's sums exact in FP64; the fraction word
+// rounds each term to 2^(aexp[k] - 2 S), below 2^-70 of the largest term for
+// n up to 2^24.  A non-finite term sets
+// aflag[k] (the output is then NaN).  k_adj_out turns the words into grad_a.
 constexpr int kRenormSteps = 256;   // products by conj(w) between two folds of the term mantissa
 
+// ---- cross-lane sums for four indices at a time, without the LDS crossbar:
+// the gfx950 half swaps v_permlane32_swap (lanes 32..63 of the first operand
+// with lanes 0..31 of the second) and v_permlane16_swap (odd rows of the first
+// with even rows of the second) bring index r's values into row r (lanes
+// 16 r .. 16 r + 15), and DPP row shifts sum each row into its lane 15.
+template <class F>
+__device__ __forceinline__ void swap32(F &a, F &b);
+template <>
+__device__ __forceinline__ void swap32<int>(int &a, int &b) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+    a = (int)r[0];
+    b = (int)r[1];
+}
+template <>
+__device__ __forceinline__ void swap32<double>(double &a, double &b) {
+    const long long A = __double_as_longlong(a), B = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)A, (unsigned)B, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(A >> 32), (unsigned)(B >> 32), false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+template <class F>
+__device__ __forceinline__ void swap16(F &a, F &b);
+template <>
+__device__ __forceinline__ void swap16<int>(int &a, int &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+    a = (int)r[0];
+    b = (int)r[1];
+}
+template <>
+__device__ __forceinline__ void swap16<double>(double &a, double &b) {
+    const long long A = __double_as_longlong(a), B = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)A, (unsigned)B, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(A >> 32), (unsigned)(B >> 32), false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+// x from lane i - n of the same row (lanes before the row's n-th: 0.0)
+template <int N>
+__device__ __forceinline__ double row_shr(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x110 + N, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + N, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int N>
+__device__ __forceinline__ int row_shr_max(int x) {
+    return max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x110 + N, 0xf, 0xf, false));
+}
+
+// per lane four values v[0..3] (one per index): returns in lane 16 r + 15 the
+// sum (ADD) or the largest value over the 64 lanes of index r
+template <class F, bool ADD>
+__device__ __forceinline__ F reduce4(F v0, F v1, F v2, F v3) {
+    swap32(v0, v2);
+    swap32(v1, v3);
+    F a = ADD ? v0 + v2 : max(v0, v2), b = ADD ? v1 + v3 : max(v1, v3);   // rows 0, 1: indices 0, 1; rows 2, 3: 2, 3
+    swap16(a, b);
+    F x = ADD ? a + b : max(a, b);                                         // row r: index r
+    if constexpr (ADD) {
+        x += row_shr<1>(x);
+        x += row_shr<2>(x);
+        x += row_shr<4>(x);
+        x += row_shr<8>(x);
+    } else {
+        x = row_shr_max<1>(x);
+        x = row_shr_max<2>(x);
+        x = row_shr_max<4>(x);
+        x = row_shr_max<8>(x);
+    }
+    return x;
+}
+
+// the exponent bound of a wavefront term (clamped far outside the FP64 range)
+__device__ __forceinline__ int term_bound(double gam, double lam, int k) {
+    const double b = ceil(fma((double)k, lam, gam));
+    return (int)fmin(4000.0, fmax(-4000.0, b)) + 2;
+}
+
+// v 2^sh in fixed point: its integer part h and S fraction bits l, both
+// integers held exactly in doubles (|h| < 2^(S - 2), |l| <= 2^S with S <= 47,
+// so sums of 64 of them stay exact in FP64); l is rounded when v 2^sh has bits
+// below 2^-S
+__device__ __forceinline__ void to_fixed(double v, int sh, int S, double &h, double &l) {
+    const double x = ldexp(v, sh);
+    h = trunc(x);
+    l = rint(ldexp(x - h, S));
+}
+
+// the passes of k_adjoint and k_adj_zero: the bounds, the exact sums, or (the
+// atomic mode) the wavefront sums added to grad_a with FP64 atomics
+enum AdjPass { kAdjBound = 0, kAdjExact = 1, kAdjAtomic = 2 };
+
+template <int MODE>
 __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const double2 *__restrict__ gin,
-                                                            const long long *__restrict__ gexp,
+                                                            const long long *__restrict__ gexp, AdjAcc A, int S,
                                                             double2 *__restrict__ grad_a, EvalWs W) {
+    constexpr bool BOUND = MODE == kAdjBound;
     const int lane = threadIdx.x % kWave;
     const int w = blockIdx.x * kWindowWaves + threadIdx.x / kWave;
     __shared__ double s_ch[4][kWindowThreads];
@@ -1820,6 +1931,10 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                 eg = (int)(x < -1000000000LL ? -1000000000LL : (x > 1000000000LL ? 1000000000LL : x));
             }
         }
+        // BOUND: |g| < 2^(eg + 1/2) for a finite nonzero g (no term otherwise)
+        const bool gterm = valid && (gr != 0.0 || gi != 0.0);
+        const double gam = (double)eg + 1.0;
+        const double lam = valid ? log2_abs(rc.z) : 0.0;
         PowState pw;
         for (;;) {
             const int c0 = c * C, c1 = c0 + C - 1;
@@ -1827,7 +1942,27 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
             const bool act = valid && lo <= hi;
             const int Khi = __builtin_amdgcn_readfirstlane(wave_max(act ? hi : INT_MIN));
             const int Klo = __builtin_amdgcn_readfirstlane(wave_min(act ? lo : INT_MAX));
-            if (Khi >= Klo) {
+            if (BOUND && Khi >= Klo) {
+                // the largest bound per k
+                for (int k0 = Klo; k0 <= Khi; k0 += 4) {
+                    int e[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = k0 + j;
+                        e[j] = (gterm && act && k >= lo && k <= hi) ? term_bound(gam, lam, k) : INT_MIN;
+                    }
+                    const int x = reduce4<int, false>(e[0], e[1], e[2], e[3]);
+                    const int k = k0 + (lane >> 4);
+                    // (most wavefronts find the bound already reached: they
+                    // read it instead of contending for the address)
+                    if ((lane & 15) == 15 && k <= Khi && x != INT_MIN &&
+                        x > __hip_atomic_load(A.aexp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        const double2 a = P.coef[k];
+                        if (a.x != 0.0 || a.y != 0.0) atomicMax(A.aexp + k, x);
+                    }
+                }
+            }
+            if (!BOUND && Khi >= Klo) {
                 const int t = threadIdx.x;
                 double pr, pi;
                 long long pe;
@@ -1841,10 +1976,8 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                 double tr = fma(gr, pr, gi * pi);
                 double ti = fma(gi, pr, -gr * pi);
                 long long E = (long long)eg + pe + (long long)lo * ez;
-                // four indices at a time: each lane's four terms, then a
-                // reduce-scatter over the wavefront (xor 32 and 16 leave lanes
-                // 16 q .. 16 q + 15 with index q; xor 8, 4, 2, 1 sum those)
-                const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+                // four indices at a time: each lane's four terms, then their
+                // sums over the wavefront (reduce4)
                 for (int k0 = Klo; k0 <= Khi; k0 += 4) {
                     if (((k0 - Klo) & (kRenormSteps - 1)) == 0 && k0 != Klo) {
                         // exact: a power of two moves from the mantissa to E
@@ -1856,45 +1989,89 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                             E += ex;
                         }
                     }
-                    double vr[4], vi[4];
+                    if constexpr (MODE == kAdjAtomic) {
+                        // the terms as they are, their wavefront sums (fixed
+                        // order) added to grad_a with FP64 atomics
+                        double vr[4], vi[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int k = k0 + j;
+                            vr[j] = 0.0;
+                            vi[j] = 0.0;
+                            if (act && k >= lo && k <= hi) {
+                                const int sh = (int)(E < -2200 ? -2200 : (E > 2200 ? 2200 : E));
+                                vr[j] = ldexp(tr, sh);
+                                vi[j] = ldexp(ti, sh);
+                                const double nr = fma(tr, wr, ti * wi);       // times conj(w)
+                                ti = fma(ti, wr, -tr * wi);
+                                tr = nr;
+                                E += ez;
+                            }
+                        }
+                        const double xr = reduce4<double, true>(vr[0], vr[1], vr[2], vr[3]);
+                        const double xi = reduce4<double, true>(vi[0], vi[1], vi[2], vi[3]);
+                        const int k = k0 + (lane >> 4);
+                        if ((lane & 15) == 15 && k <= Khi && (xr != 0.0 || xi != 0.0)) {
+                            const double2 a = P.coef[k];
+                            if (a.x != 0.0 || a.y != 0.0) {
+                                atomicAdd(&grad_a[k].x, xr);
+                                atomicAdd(&grad_a[k].y, xi);
+                            }
+                        }
+                        continue;
+                    }
+                    // each term to fixed point relative to its index's scale
+                    // 2^aexp[k] (four words: integer and fraction parts of
+                    // Re and Im), so that every sum below is exact
+                    int ek[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        ek[j] = k0 + j <= Khi ? __builtin_amdgcn_readfirstlane(A.aexp[k0 + j]) : 0;
+                    double wv[4][4];
+                    int bad = 0;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int k = k0 + j;
-                        vr[j] = 0.0;
-                        vi[j] = 0.0;
+                        wv[j][0] = wv[j][1] = wv[j][2] = wv[j][3] = 0.0;
                         if (act && k >= lo && k <= hi) {
                             const int sh = (int)(E < -2200 ? -2200 : (E > 2200 ? 2200 : E));
-                            vr[j] = ldexp(tr, sh);
-                            vi[j] = ldexp(ti, sh);
+                            const double vr = ldexp(tr, sh), vi = ldexp(ti, sh);
+                            if (!isfinite(vr) || !isfinite(vi)) {
+                                bad |= 1 << j;
+                            } else if (vr != 0.0 || vi != 0.0) {
+                                const int fs = max(-2200, min(2200, S - ek[j]));
+                                to_fixed(vr, fs, S, wv[j][0], wv[j][1]);
+                                to_fixed(vi, fs, S, wv[j][2], wv[j][3]);
+                            }
                             const double nr = fma(tr, wr, ti * wi);       // times conj(w)
                             ti = fma(ti, wr, -tr * wi);
                             tr = nr;
                             E += ez;
                         }
                     }
-                    // xor 32: keep indices {0, 1} (b5 clear) or {2, 3}, add the partner's
-                    double ar = b5 ? vr[2] : vr[0], ai = b5 ? vi[2] : vi[0];
-                    double br = b5 ? vr[3] : vr[1], bi = b5 ? vi[3] : vi[1];
-                    ar += __shfl_xor(b5 ? vr[0] : vr[2], 32, kWave);
-                    ai += __shfl_xor(b5 ? vi[0] : vi[2], 32, kWave);
-                    br += __shfl_xor(b5 ? vr[1] : vr[3], 32, kWave);
-                    bi += __shfl_xor(b5 ? vi[1] : vi[3], 32, kWave);
-                    // xor 16: keep the first (b4 clear) or the second of the pair
-                    double xr = b4 ? br : ar, xi = b4 ? bi : ai;
-                    xr += __shfl_xor(b4 ? ar : br, 16, kWave);
-                    xi += __shfl_xor(b4 ? ai : bi, 16, kWave);
-                    for (int o = 8; o > 0; o >>= 1) {
-                        xr += __shfl_xor(xr, o, kWave);
-                        xi += __shfl_xor(xi, o, kWave);
-                    }
-                    const int k = k0 + ((lane >> 4) & 3);
+                    // the 64 lanes' words per index (sums of integers below
+                    // 2^53: exact in any order)
+                    double x[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) x[q] = reduce4<double, true>(wv[0][q], wv[1][q], wv[2][q], wv[3][q]);
+                    const int k = k0 + (lane >> 4);
                     // only terms of G_p: their coefficients are the nonzero
                     // entries of the masked table
-                    if ((lane & 15) == 0 && k <= Khi && (xr != 0.0 || xi != 0.0)) {
+                    if ((lane & 15) == 15 && k <= Khi && (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0 || x[3] != 0.0)) {
                         const double2 a = P.coef[k];
                         if (a.x != 0.0 || a.y != 0.0) {
-                            atomicAdd(&grad_a[k].x, xr);
-                            atomicAdd(&grad_a[k].y, xi);
+                            unsigned long long *wd = reinterpret_cast<unsigned long long *>(A.acc + 4 * (size_t)k);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (x[q] != 0.0) atomicAdd(wd + q, (unsigned long long)(long long)x[q]);
+                        }
+                    }
+                    // a non-finite term makes its index NaN
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (__ballot((bad >> j) & 1) != 0 && lane == 0) {
+                            const double2 a = P.coef[k0 + j];
+                            if (a.x != 0.0 || a.y != 0.0) atomicOr(A.aflag + k0 + j, 1);
                         }
                     }
                 }
@@ -1912,32 +2089,133 @@ __global__ __launch_bounds__(256) void k_zero2(double2 *__restrict__ x, int64_t 
     if (i < n) x[i] = make_double2(0.0, 0.0);
 }
 
+// grad_a's accumulators start empty: no bound, no flag, zero words
+__global__ __launch_bounds__(256) void k_adj_init(AdjAcc A, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    A.aexp[i] = INT_MIN;
+    A.aflag[i] = 0;
+    longlong2 *w = reinterpret_cast<longlong2 *>(A.acc + 4 * i);
+    w[0] = make_longlong2(0, 0);
+    w[1] = make_longlong2(0, 0);
+}
+
+// The points z = 0 (no window; their kept term is a_0 alone when a_0 != 0):
+// grad_a[0] += gin 2^-gexp.  With BOUND, aexp[0] rises to the terms' bound;
+// then each term goes to fixed point like k_adjoint's, and each workgroup adds
+// the integer sum of its points' words (exact).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_adj_zero(DevPlan P, const double2 *__restrict__ z, int n,
+                                                  const double2 *__restrict__ gin, const long long *__restrict__ gexp,
+                                                  AdjAcc A, int S, double2 *__restrict__ grad_a) {
+    constexpr bool BOUND = MODE == kAdjBound;
+    __shared__ long long s_w[4][256];
+    __shared__ int s_e[256];
+    __shared__ double s_d[2][256];
+    const int t = threadIdx.x, j = blockIdx.x * 256 + t;
+    double vr = 0.0, vi = 0.0;
+    bool term = false;
+    if (j < n && P.nh > 0 && P.v == 0) {
+        const double2 zz = z[j];
+        if (zz.x == 0.0 && zz.y == 0.0) {
+            const double2 g = gin[j];
+            const long long gx = gexp ? gexp[j] : 0;
+            const int sh = (int)(gx > 2200 ? 2200 : (gx < -2200 ? -2200 : gx));
+            vr = ldexp(g.x, -sh);
+            vi = ldexp(g.y, -sh);
+            term = vr != 0.0 || vi != 0.0;
+        }
+    }
+    const double m = fmax(fabs(vr), fabs(vi));
+    if (BOUND) {
+        // |v| < 2^(exp_of(m) + 1/2): the same margin as term_bound
+        s_e[t] = term && isfinite(m) ? exp_of(m) + 3 : INT_MIN;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) s_e[t] = max(s_e[t], s_e[t + o]);
+            __syncthreads();
+        }
+        if (t == 0 && s_e[0] != INT_MIN) atomicMax(A.aexp, s_e[0]);
+        return;
+    }
+    if constexpr (MODE == kAdjAtomic) {
+        s_d[0][t] = vr;
+        s_d[1][t] = vi;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) { s_d[0][t] += s_d[0][t + o]; s_d[1][t] += s_d[1][t + o]; }
+            __syncthreads();
+        }
+        if (t == 0 && (s_d[0][0] != 0.0 || s_d[1][0] != 0.0)) {
+            atomicAdd(&grad_a[0].x, s_d[0][0]);
+            atomicAdd(&grad_a[0].y, s_d[1][0]);
+        }
+        return;
+    }
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool bad = term && !isfinite(m);
+    if (term && !bad) {
+        const int fs = max(-2200, min(2200, S - A.aexp[0]));
+        to_fixed(vr, fs, S, w[0], w[1]);
+        to_fixed(vi, fs, S, w[2], w[3]);
+    }
+    for (int q = 0; q < 4; ++q) s_w[q][t] = (long long)w[q];
+    if (__syncthreads_or(bad) && t == 0) atomicOr(A.aflag, 1);
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o)
+            for (int q = 0; q < 4; ++q) s_w[q][t] += s_w[q][t + o];
+        __syncthreads();
+    }
+    if (t == 0) {
+        unsigned long long *wd = reinterpret_cast<unsigned long long *>(A.acc);
+        for (int q = 0; q < 4; ++q)
+            if (s_w[q][0] != 0) atomicAdd(wd + q, (unsigned long long)s_w[q][0]);
+    }
+}
+
+// one component of grad_a[k] from its two words: (h 2^S + l) 2^(aexp - 2 S)
+__device__ __forceinline__ double fixed_value(long long h, long long l, int S, int E) {
+    const long long t = h + (l >> S);                  // l = (l >> S) 2^S + r, 0 <= r < 2^S
+    const long long r = l - ((l >> S) << S);
+    const double v = fma((double)t, ldexp(1.0, S), (double)r);
+    return ldexp(v, max(-2200, min(2200, E - 2 * S)));
+}
+
+__global__ __launch_bounds__(256) void k_adj_out(AdjAcc A, int64_t nacc, int64_t n, int S,
+                                                 double2 *__restrict__ grad_a) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    double2 v = make_double2(0.0, 0.0);
+    if (k < nacc) {
+        const int E = A.aexp[k];
+        if (A.aflag[k]) {
+            v = make_double2(__builtin_nan(""), __builtin_nan(""));
+        } else if (E != INT_MIN) {
+            const long long *w = A.acc + 4 * k;
+            v = make_double2(fixed_value(w[0], w[1], S, E), fixed_value(w[2], w[3], S, E));
+        }
+    }
+    grad_a[k] = v;
+}
+
 // Per point: the gradient with respect to z, gin conj(Q'(z)) with Q' = md 2^ed
-// (NaN for a non-finite z), and the contribution of z = 0 to a_0: there the
-// kept terms are a_0 alone (when a_0 != 0), so grad_a[0] += gin.
-__global__ __launch_bounds__(256) void k_grad_z(DevPlan P, const double2 *__restrict__ z, int n,
+// (NaN for a non-finite z).
+__global__ __launch_bounds__(256) void k_grad_z(const double2 *__restrict__ z, int n,
                                                 const double2 *__restrict__ gin, const long long *__restrict__ gexp,
                                                 const double2 *__restrict__ md, const long long *__restrict__ ed,
-                                                double2 *__restrict__ grad_z, double2 *__restrict__ grad_a) {
+                                                double2 *__restrict__ grad_z) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const double2 zz = z[j];
     double2 g = gin[j];
     const long long gx = gexp ? gexp[j] : 0;
-    if (grad_z) {
-        if (!isfinite(zz.x) || !isfinite(zz.y)) {
-            grad_z[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
-        } else {
-            const double2 b = md[j];
-            long long sh = ed[j] - gx;
-            sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
-            grad_z[j] = make_double2(ldexp(fma(g.x, b.x, g.y * b.y), (int)sh), ldexp(fma(g.y, b.x, -g.x * b.y), (int)sh));
-        }
-    }
-    if (grad_a && zz.x == 0.0 && zz.y == 0.0 && P.nh > 0 && P.v == 0) {
-        const int sh = (int)(gx > 2200 ? 2200 : (gx < -2200 ? -2200 : gx));
-        atomicAdd(&grad_a[0].x, ldexp(g.x, -sh));
-        atomicAdd(&grad_a[0].y, ldexp(g.y, -sh));
+    if (!isfinite(zz.x) || !isfinite(zz.y)) {
+        grad_z[j] = make_double2(__builtin_nan(""), __builtin_nan(""));
+    } else {
+        const double2 b = md[j];
+        long long sh = ed[j] - gx;
+        sh = sh < -2200 ? -2200 : (sh > 2200 ? 2200 : sh);
+        grad_z[j] = make_double2(ldexp(fma(g.x, b.x, g.y * b.y), (int)sh), ldexp(fma(g.y, b.x, -g.x * b.y), (int)sh));
     }
 }
 
@@ -1989,7 +2267,7 @@ hipError_t device_setup() {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const void *kern[kTileKinds] = {reinterpret_cast<const void *>(k_window<false, false>),
                                     reinterpret_cast<const void *>(k_window<true, false>),
-                                    reinterpret_cast<const void *>(k_adjoint),
+                                    reinterpret_cast<const void *>(k_adjoint<kAdjExact>),
                                     reinterpret_cast<const void *>(k_window<false, true>),
                                     reinterpret_cast<const void *>(k_window<false, false, true>),
                                     reinterpret_cast<const void *>(k_window<false, false, false, true>),
@@ -2157,6 +2435,11 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.lacc = (long long *)take(sizeof(long long) * kSlotWords * kWave * nlong);
     w.lcnt = (int32_t *)take(sizeof(int32_t) * nlong);
     w.ctl = (int32_t *)take(sizeof(int32_t) * 64);
+    // the reverse mode's accumulators (a layout for the values alone has none)
+    w.n_acc = (!tight || kind == kTileAdjoint) ? std::max<int64_t>((int64_t)P.dt + 1, 1) : 0;
+    w.aexp = (int32_t *)take(sizeof(int32_t) * std::max<int64_t>(w.n_acc, 1));
+    w.aflag = (int32_t *)take(sizeof(int32_t) * std::max<int64_t>(w.n_acc, 1));
+    w.aacc = (long long *)take(sizeof(long long) * 4 * std::max<int64_t>(w.n_acc, 1));
     w.n = n;
     w.tab_ib = tab_ib;
     w.cost_shift = cost_shift_for(P, n, chunk);
@@ -2487,25 +2770,45 @@ extern "C" fpe_status fpe_eval_adjoint(fpe_plan_t plan, const double *z_dev, int
     const int64_t na = plan->d + 1;
     double2 *ga = reinterpret_cast<double2 *>(grad_a_dev);
     FPE_HIP_CHECK(device_setup());
-    if (ga) k_zero2<<<(unsigned)((na + 255) / 256), 256, 0, stream>>>(ga, na);
-    if (n > 0) {
-        EvalWs W;
-        eval_workspace_bytes(P, n, &W, workspace_dev, kTileAdjoint, -1, plan_chunk(plan, n));
-        const double2 *z = reinterpret_cast<const double2 *>(z_dev);
-        const double2 *g = reinterpret_cast<const double2 *>(g_dev);
-        const int ni = (int)n;
-        if (ga) {
+    EvalWs W;
+    eval_workspace_bytes(P, n, &W, workspace_dev, kTileAdjoint, -1, plan_chunk(plan, n));
+    const AdjAcc A{W.aexp, W.aflag, W.aacc};
+    // fraction bits of the fixed point: an index gathers at most one term per
+    // point, each below 2^(S - 2) in units of its scale, so n 2^S <= 2^62;
+    // and S <= 47 keeps a wavefront's sums of 64 terms exact in FP64
+    int S = 62;
+    for (int64_t cnt = n; cnt > 0; cnt >>= 1) --S;
+    S = std::min(S, 47);
+    const double2 *z = reinterpret_cast<const double2 *>(z_dev);
+    const double2 *g = reinterpret_cast<const double2 *>(g_dev);
+    const long long *gx = reinterpret_cast<const long long *>(g_exp_dev);
+    const int ni = (int)n;
+    const unsigned pb = (unsigned)((n + 255) / 256);
+    if (ga && plan->adjoint_mode == FPE_ADJOINT_ATOMIC) {
+        k_zero2<<<(unsigned)((na + 255) / 256), 256, 0, stream>>>(ga, na);
+        if (n > 0) {
             FPE_HIP_CHECK(launch_front(P, z, ni, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, stream));
-            if (P.nh > 0)
-                k_adjoint<<<(unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves), kWindowThreads, 0, stream>>>(
-                    P, g, reinterpret_cast<const long long *>(g_exp_dev), ga, W);
+            const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
+            if (P.nh > 0) k_adjoint<kAdjAtomic><<<wb, kWindowThreads, 0, stream>>>(P, g, gx, A, S, ga, W);
+            k_adj_zero<kAdjAtomic><<<pb, 256, 0, stream>>>(P, z, ni, g, gx, A, S, ga);
         }
-        if (ga || grad_z_dev)
-            k_grad_z<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
-                P, z, ni, g, reinterpret_cast<const long long *>(g_exp_dev), reinterpret_cast<const double2 *>(md_dev),
-                reinterpret_cast<const long long *>(ed_dev),
-                reinterpret_cast<double2 *>(grad_z_dev), ga);
+    } else if (ga) {
+        // (with no points the workspace may be absent: grad_a is only zeroed)
+        if (n > 0) {
+            k_adj_init<<<(unsigned)((W.n_acc + 255) / 256), 256, 0, stream>>>(A, W.n_acc);
+            FPE_HIP_CHECK(launch_front(P, z, ni, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, stream));
+            const unsigned wb = (unsigned)((W.n_waves + kWindowWaves - 1) / kWindowWaves);
+            if (P.nh > 0) k_adjoint<kAdjBound><<<wb, kWindowThreads, 0, stream>>>(P, g, gx, A, S, ga, W);
+            k_adj_zero<kAdjBound><<<pb, 256, 0, stream>>>(P, z, ni, g, gx, A, S, ga);
+            if (P.nh > 0) k_adjoint<kAdjExact><<<wb, kWindowThreads, 0, stream>>>(P, g, gx, A, S, ga, W);
+            k_adj_zero<kAdjExact><<<pb, 256, 0, stream>>>(P, z, ni, g, gx, A, S, ga);
+        }
+        k_adj_out<<<(unsigned)((na + 255) / 256), 256, 0, stream>>>(A, n > 0 ? W.n_acc : 0, na, S, ga);
     }
+    if (n > 0 && grad_z_dev)
+        k_grad_z<<<pb, 256, 0, stream>>>(z, ni, g, gx, reinterpret_cast<const double2 *>(md_dev),
+                                         reinterpret_cast<const long long *>(ed_dev),
+                                         reinterpret_cast<double2 *>(grad_z_dev));
     FPE_HIP_CHECK(hipGetLastError());
     set_error("");
     return FPE_OK;
@@ -2764,6 +3067,14 @@ extern "C" fpe_status fpe_plan_set_window_mode(fpe_plan_t plan, int32_t mode) {
     if (mode == FPE_WINDOW_SPARSE && plan->dev.coef32)
         return fail(FPE_ERR_UNSUPPORTED, "FP32 plans sum their windows in the dense form");
     plan->mode_sel = mode;
+    set_error("");
+    return FPE_OK;
+}
+
+extern "C" fpe_status fpe_plan_set_adjoint_mode(fpe_plan_t plan, int32_t mode) {
+    if (!plan) return fail(FPE_ERR_INVALID_ARG, "NULL plan");
+    if (mode != FPE_ADJOINT_EXACT && mode != FPE_ADJOINT_ATOMIC) return fail(FPE_ERR_INVALID_ARG, "unknown adjoint mode");
+    plan->adjoint_mode = mode;
     set_error("");
     return FPE_OK;
 }

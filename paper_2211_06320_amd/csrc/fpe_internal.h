@@ -93,6 +93,19 @@ struct EvalWs {
     // in 1/256 (256 for dense window sums)
     int32_t sparse;
     int32_t *gdens;
+    // the reverse mode's exact accumulators of grad_a, one per coefficient
+    // index up to dt (absent from a layout sized for the values alone)
+    int32_t *aexp, *aflag;
+    long long *aacc;
+    int64_t n_acc;
+};
+
+// The reverse mode's accumulators, as kernel arguments: per coefficient index
+// the exponent of the fixed-point scale, a non-finite flag, and four words
+// (integer and fraction words of the real, then of the imaginary part).
+struct AdjAcc {
+    int32_t *aexp, *aflag;
+    long long *acc;
 };
 
 // tight: the per-wavefront tables sized for this kind of tile kernel alone (by
@@ -297,6 +310,7 @@ struct fpe_plan_s {
     int device;
     int32_t chunk_sel = 0;           // chunk length chosen by fpe_autotune or set; 0: cached choice or default
     int32_t mode_sel = 0;            // window-sum form chosen or set (FPE_WINDOW_*); 0: cached choice or default
+    int32_t adjoint_mode = 0;        // FPE_ADJOINT_EXACT (0) or FPE_ADJOINT_ATOMIC
 };
 
 namespace fpe {
