@@ -90,6 +90,29 @@ __device__ __forceinline__ void normalise(double re, double im, long long E, dou
     e = E + k;
 }
 
+// The smallest / largest value over the 64 lanes, in every lane: the gfx950
+// half swaps (v_permlane32_swap: lanes 32..63 of one operand with lanes 0..31
+// of the other; v_permlane16_swap: odd rows with even rows) leave in each row
+// the extremes over lanes i, i + 16, i + 32, i + 48, and DPP row shifts take
+// the row's extreme into its lane 15 (no LDS crossbar round trips).  Every
+// lane of the wavefront must be active.
+template <bool MAX>
+__device__ __forceinline__ int wave_ext(int v) {
+    auto ext = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    v = ext((int)r[0], (int)r[1]);
+    r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    v = ext((int)r[0], (int)r[1]);
+    constexpr int id = MAX ? INT_MIN : INT_MAX;
+    v = ext(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = ext(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = ext(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = ext(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    return __builtin_amdgcn_readlane(v, 15);
+}
+__device__ __forceinline__ int wave_min(int v) { return wave_ext<false>(v); }
+__device__ __forceinline__ int wave_max(int v) { return wave_ext<true>(v); }
+
 // global exclusive prefix of the finished-points bin = number of points with a window
 __device__ __forceinline__ int valid_points(const EvalWs &W) {
     if (W.n_slots >= 0) return (int)W.n_slots;      // a batch: every slot, padding included

@@ -290,16 +290,6 @@ __host__ __device__ __forceinline__ void cpow_chunk_start(double wr, double wi, 
     for (int j = m; j < c; ++j) cmul_renorm(xr, xi, xe, zcr, zci, zce);
 }
 
-// wave-wide reductions over the 64 lanes
-__device__ __forceinline__ int wave_min(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 }  // namespace fpe
 
 // Host-side plan handle (the ABI's opaque fpe_plan_s).

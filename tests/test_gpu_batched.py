@@ -53,9 +53,15 @@ def mixed_batch(seed):
 
 
 def run_batch(fpe, coeffs, points, fp32=False, p=53):
+    # the chunk length pinned on every plan and on the batch: bit-for-bit
+    # agreement holds for equal chunk lengths, and an earlier autotune in the
+    # process may have cached another choice for some plan's size bucket
     plans = [fpe.precondition(to_dev(c), p, fp32=fp32) for c in coeffs]
+    for pl in plans:
+        pl.set_chunk(512)
     offs = np.concatenate([[0], np.cumsum([len(z) for z in points])])
     batch = fpe.Batch(plans, offs)
+    batch.set_chunk(512)
     zall = np.concatenate(points) if len(points) else np.zeros(0, np.complex128)
     m, e, t = batch.eval(to_dev(zall), terms=True)
     torch.cuda.synchronize()
