@@ -1976,10 +1976,10 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                     }
                     const int x = reduce4<int, false>(e[0], e[1], e[2], e[3]);
                     const int k = k0 + (lane >> 4);
-                    // (most wavefronts find the bound already reached: they
-                    // read it instead of contending for the address)
-                    if ((lane & 15) == 15 && k <= Khi && x != INT_MIN &&
-                        x > __hip_atomic_load(A.aexp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    // (a read of the current bound before the atomic, to skip
+                    // it where the bound is reached, measured slower: the
+                    // read's latency is exposed at every step)
+                    if ((lane & 15) == 15 && k <= Khi && x != INT_MIN) {
                         const double2 a = P.coef[k];
                         if (a.x != 0.0 || a.y != 0.0) atomicMax(A.aexp + k, x);
                     }
