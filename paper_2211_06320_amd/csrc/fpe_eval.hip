@@ -1886,6 +1886,21 @@ __device__ __forceinline__ F reduce4(F v0, F v1, F v2, F v3) {
     return x;
 }
 
+// which of k0 .. k0 + 3 (at most khi) are in G_p (the nonzero entries of the
+// masked table), as 4 bits: wave-uniform indices, so scalar loads, issued at
+// the top of a step and waited for only where the sums are added
+__device__ __forceinline__ int gp_mask4(const DevPlan &P, int k0, int khi) {
+    const_table_t cf = (const_table_t)P.coef;
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = min(k0 + j, khi);
+        const double re = cf[2 * k], im = cf[2 * k + 1];
+        if (k0 + j <= khi && (re != 0.0 || im != 0.0)) m |= 1 << j;
+    }
+    return m;
+}
+
 // the exponent bound of a wavefront term (clamped far outside the FP64 range)
 __device__ __forceinline__ int term_bound(double gam, double lam, int k) {
     const double b = ceil(fma((double)k, lam, gam));
@@ -1968,6 +1983,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
             if (BOUND && Khi >= Klo) {
                 // the largest bound per k
                 for (int k0 = Klo; k0 <= Khi; k0 += 4) {
+                    const int gm = gp_mask4(P, k0, Khi);
                     int e[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
@@ -1979,10 +1995,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                     // (a read of the current bound before the atomic, to skip
                     // it where the bound is reached, measured slower: the
                     // read's latency is exposed at every step)
-                    if ((lane & 15) == 15 && k <= Khi && x != INT_MIN) {
-                        const double2 a = P.coef[k];
-                        if (a.x != 0.0 || a.y != 0.0) atomicMax(A.aexp + k, x);
-                    }
+                    if ((lane & 15) == 15 && ((gm >> (lane >> 4)) & 1) && x != INT_MIN) atomicMax(A.aexp + k, x);
                 }
             }
             if (!BOUND && Khi >= Klo) {
@@ -2012,6 +2025,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                             E += ex;
                         }
                     }
+                    const int gm = gp_mask4(P, k0, Khi);
                     if constexpr (MODE == kAdjAtomic) {
                         // the terms as they are, their wavefront sums (fixed
                         // order) added to grad_a with FP64 atomics
@@ -2034,12 +2048,9 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                         const double xr = reduce4<double, true>(vr[0], vr[1], vr[2], vr[3]);
                         const double xi = reduce4<double, true>(vi[0], vi[1], vi[2], vi[3]);
                         const int k = k0 + (lane >> 4);
-                        if ((lane & 15) == 15 && k <= Khi && (xr != 0.0 || xi != 0.0)) {
-                            const double2 a = P.coef[k];
-                            if (a.x != 0.0 || a.y != 0.0) {
-                                atomicAdd(&grad_a[k].x, xr);
-                                atomicAdd(&grad_a[k].y, xi);
-                            }
+                        if ((lane & 15) == 15 && ((gm >> (lane >> 4)) & 1) && (xr != 0.0 || xi != 0.0)) {
+                            atomicAdd(&grad_a[k].x, xr);
+                            atomicAdd(&grad_a[k].y, xi);
                         }
                         continue;
                     }
@@ -2080,22 +2091,17 @@ __global__ __launch_bounds__(kWindowThreads) void k_adjoint(DevPlan P, const dou
                     const int k = k0 + (lane >> 4);
                     // only terms of G_p: their coefficients are the nonzero
                     // entries of the masked table
-                    if ((lane & 15) == 15 && k <= Khi && (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0 || x[3] != 0.0)) {
-                        const double2 a = P.coef[k];
-                        if (a.x != 0.0 || a.y != 0.0) {
-                            unsigned long long *wd = reinterpret_cast<unsigned long long *>(A.acc + 4 * (size_t)k);
+                    if ((lane & 15) == 15 && ((gm >> (lane >> 4)) & 1) &&
+                        (x[0] != 0.0 || x[1] != 0.0 || x[2] != 0.0 || x[3] != 0.0)) {
+                        unsigned long long *wd = reinterpret_cast<unsigned long long *>(A.acc + 4 * (size_t)k);
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                if (x[q] != 0.0) atomicAdd(wd + q, (unsigned long long)(long long)x[q]);
-                        }
+                        for (int q = 0; q < 4; ++q)
+                            if (x[q] != 0.0) atomicAdd(wd + q, (unsigned long long)(long long)x[q]);
                     }
                     // a non-finite term makes its index NaN
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        if (__ballot((bad >> j) & 1) != 0 && lane == 0) {
-                            const double2 a = P.coef[k0 + j];
-                            if (a.x != 0.0 || a.y != 0.0) atomicOr(A.aflag + k0 + j, 1);
-                        }
+                        if (__ballot((bad >> j) & 1) != 0 && lane == 0 && ((gm >> j) & 1)) atomicOr(A.aflag + k0 + j, 1);
                     }
                 }
             }
