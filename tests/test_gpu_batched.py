@@ -137,6 +137,22 @@ def test_batched_workload_4096(fpe):
     assert worst <= TOL
 
 
+def test_batched_workload_4096_fp32(fpe):
+    """The 4096-polynomial workload with FP32 plans (p = 24): within 2^-18 of
+    the oracle at p = 24 on 12 sampled polynomials."""
+    coeffs, points = workloads.batched_workload()
+    plans, offs, zall, m, e, t = run_batch(fpe, coeffs, points, fp32=True, p=24)
+    rng = np.random.default_rng(19)
+    worst = 0.0
+    for i in rng.choice(len(coeffs), 12, replace=False):
+        sl = slice(offs[i], offs[i + 1])
+        ref = oracle.precondition(coeffs[i], 24).eval(points[i])
+        err = oracle.scaled_error(m[sl], e[sl], ref["m"], ref["e"], ref["dwin_m"], ref["dwin_e"])
+        worst = max(worst, float(err.max()))
+    say(f"  4096 polynomials with FP32 plans: max scaled error on 12 sampled polynomials {worst:.3e}")
+    assert worst <= 2.0 ** -18
+
+
 def test_batched_limits(fpe):
     c = to_dev(workloads.uniform_coeffs(50, 3))
     p = fpe.precondition(c, 53)

@@ -112,6 +112,13 @@ def test_deriv_full_size(fpe):
     check(fpe, wl.coeffs, wl.points, sample=400, label="d=1e6 sample")
 
 
+def test_deriv_adjoint_workload_sample(fpe):
+    """Q and Q' at all 2^20 points of the reverse-mode workload (d = 2^18),
+    checked against the oracle on 400 sampled points."""
+    wl = workloads.workload("uniform_d2p18")
+    check(fpe, wl.coeffs, wl.points, sample=400, label="d=2^18, 2^20 points, sample")
+
+
 def test_newton_paper_example(fpe):
     """z^64 + 1 at z = 10 (Section 7.2): the kept terms are z^64 alone, the step
     is z/64, so the new point is 9.84375 exactly."""
