@@ -724,11 +724,13 @@ __device__ __forceinline__ void partition_wave(const EvalWs &W, const BlockOffse
     const long long base = bo.at(lo);
     // offsets inside a workgroup do not decrease: g is g0 plus the number of
     // the workgroup's later groups starting at or before s_w (independent
-    // loads, one memory latency instead of one per group)
+    // loads, one memory latency instead of one per group: the indices are
+    // clamped rather than the loads guarded, which the compiler would turn
+    // into one branch and one wait per load)
     const int g0 = lo * kGroupsPerBlock, ng = min(G - g0, kGroupsPerBlock);
     int32_t cum[kGroupsPerBlock];
 #pragma unroll
-    for (int k = 1; k < kGroupsPerBlock; ++k) cum[k] = k < ng ? W.gcum[g0 + k] : 0;
+    for (int k = 1; k < kGroupsPerBlock; ++k) cum[k] = W.gcum[g0 + min(k, ng - 1)];
     int g = g0;
 #pragma unroll
     for (int k = 1; k < kGroupsPerBlock; ++k) g += (k < ng && base + cum[k] <= sw) ? 1 : 0;
@@ -740,9 +742,10 @@ __device__ __forceinline__ void partition_wave(const EvalWs &W, const BlockOffse
     // w starts inside g and g's first tile belongs to w - 1: g is split, and
     // w is its second owner (this identifies each split group once); long
     // groups have their own list
-    if (st.x == g && div_floor(A * NW, total) == w - 1 &&
-        div_floor((B - gc.last) * NW, total) - (w - 1) < kFinalShort)
-        W.split[atomicAdd(W.ctl + 8, 1)] = g;
+    if (st.x == g && div_floor(A * NW, total) == w - 1) {
+        const int wy = (int)div_floor((B - gc.last) * NW, total);
+        if (wy - (w - 1) < kFinalShort) W.split[atomicAdd(W.ctl + 8, 1)] = make_int4(g, w - 1, wy, 0);
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
@@ -773,13 +776,10 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
         // last tile's start
         const int g = (int)i;
         const int cost = W.gcost[g];
-        if (cost == 0 || total == 0) {
-            W.gwave[g] = make_int2(-1, -1);
-        } else {
+        if (cost != 0 && total != 0) {
             const GroupCost gc = group_cost(W.glo[g], W.ghi[g], W.gml[g], C, W.cost_shift, W.gdens[g]);
             const long long A = W.gcum[g] + bo.at(g / kGroupsPerBlock), B = A + cost;
             const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
-            W.gwave[g] = gw;
             if (gw.y - gw.x >= kFinalShort) {
                 const int li = atomicAdd(W.ctl + 9, 1);
                 W.lgroups[li] = make_int4(g, gw.x, gw.y, 0);
@@ -1694,12 +1694,18 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
     int npieces = 0;
     if (nlong > 0) {                                   // the same for every thread
         const int i0 = threadIdx.x * kLongPer;
-        int cnt[kLongPer];
+        int cnt[kLongPer] = {};
         int sum = 0;
+        if (i0 < nlong) {
+            // clamped indices, all loads issued before the first use
+            int4 lg[kLongPer];
 #pragma unroll
-        for (int e = 0; e < kLongPer; ++e) {
-            cnt[e] = i0 + e < nlong ? long_pieces(W.lgroups[i0 + e]) : 0;
-            sum += cnt[e];
+            for (int e = 0; e < kLongPer; ++e) lg[e] = W.lgroups[min(i0 + e, nlong - 1)];
+#pragma unroll
+            for (int e = 0; e < kLongPer; ++e) {
+                cnt[e] = i0 + e < nlong ? long_pieces(lg[e]) : 0;
+                sum += cnt[e];
+            }
         }
         int incl = sum;
 #pragma unroll
@@ -1729,10 +1735,10 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
         // the owners [wa, wb] this item sums, of group g whose first owner is wx
         int g, wx, wa, wb, li = -1, np = 0;
         if (u < nsplit) {
-            g = W.split[u];
-            const int2 gw = W.gwave[g];
-            wx = wa = gw.x;
-            wb = gw.y;
+            const int4 sp = W.split[u];
+            g = sp.x;
+            wx = wa = sp.y;
+            wb = sp.z;
         } else {
             const int pid = u - nsplit;
             int lo = 0, hi = nlong - 1;                // the first long group with s_pre > pid
@@ -2444,8 +2450,7 @@ size_t eval_workspace_bytes(const DevPlan &P, int64_t n, EvalWs *ws, void *base,
     w.gblk_pre = (int32_t *)take(sizeof(int32_t) * (nblk_g > 0 ? nblk_g : 1));
     w.gseg_sum = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
     w.gseg_off = (int32_t *)take(sizeof(int32_t) * (nseg_g > 0 ? nseg_g : 1));
-    w.gwave = (int2 *)take(sizeof(int2) * (G > 0 ? G : 1));
-    w.split = (int32_t *)take(sizeof(int32_t) * (G > 0 ? G : 1));
+    w.split = (int4 *)take(sizeof(int4) * (G > 0 ? G : 1));
     // as many window wavefronts as are resident, but no more than four per
     // group: a small evaluation then spreads its few tiles over few wavefronts
     w.n_waves = std::min<int64_t>(window_waves(kind), std::max<int64_t>(4 * G, 1));

@@ -67,9 +67,9 @@ struct EvalWs {
     int32_t *bin_sum, *bin_off;   // per table-scan segment (tab_ib bins)
     int32_t *glo, *ghi;           // per group of kWave sorted points: union window,
     int32_t *gml;                 //   largest window start,
-    int32_t *gcost, *gcum;        //   work of its tiles and its prefix within its k_groups workgroup,
-    int2 *gwave;                  //   first and last window wavefront owning its tiles
-    int32_t *split;               // groups owned by a few window wavefronts (ctl[8] of them)
+    int32_t *gcost, *gcum;        //   work of its tiles and its prefix within its k_groups workgroup
+    int4 *split;                  // groups owned by a few window wavefronts (ctl[8] of them): group,
+                                  //   first and last owner
     int4 *lgroups;                // groups owned by many (ctl[9] of them): group, first and last owner,
     long long *lacc;              //   per such group 64 lanes x kSlotWords: the sum of its slots
     int32_t *lcnt;                //   and the pieces of its owners summed so far
