@@ -255,14 +255,22 @@ class Plan:
         _check(lib().fpe_eval_workspace_size(self._h, n, ctypes.byref(nb)))
         return nb.value
 
-    def workspace(self, n: int):
-        """A cached device workspace large enough for n points."""
+    def workspace(self, n: int, stream=None):
+        """A cached device workspace large enough for n points, one per stream:
+        calls on different streams may overlap, so they never share one."""
+        torch = _torch()
         nb = self.eval_workspace_bytes(n)
-        cur = self._eval_ws.get("buf")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        key = int(s.cuda_stream)
+        cur = self._eval_ws.get(key)
         if cur is None or cur[2] < nb:
             buf, ptr = _workspace(nb, self.device)
-            self._eval_ws["buf"] = (buf, ptr, nb)
-        return self._eval_ws["buf"][1], self._eval_ws["buf"][2]
+            # the caching allocator may hand the memory out again only once the
+            # work queued on this stream is done with it
+            if s != torch.cuda.current_stream():
+                buf.record_stream(s)
+            self._eval_ws[key] = (buf, ptr, nb)
+        return self._eval_ws[key][1], self._eval_ws[key][2]
 
     def eval(self, z, terms: bool = False, window: bool = False, out=None, stream=None):
         """Q_lambda(z) for every point (Algorithm A_p, second block).
@@ -280,7 +288,7 @@ class Plan:
             m, e = out
         t = torch.empty(n, dtype=torch.int32, device=z.device) if terms else None
         w = torch.empty((n, 2), dtype=torch.int64, device=z.device) if window else None
-        ws, nb = self.workspace(n)
+        ws, nb = self.workspace(n, stream)
         _check(lib().fpe_eval(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(),
                               t.data_ptr() if t is not None else None,
                               w.data_ptr() if w is not None else None, ws, nb, _stream(stream)))
@@ -330,7 +338,7 @@ class Plan:
         n = z.shape[0]
         m = torch.empty(n, dtype=torch.complex128, device=z.device)
         e = torch.empty(n, dtype=torch.int64, device=z.device)
-        ws, nb = self.workspace(n)
+        ws, nb = self.workspace(n, stream)
         c = ctypes.c_int32()
         _check(lib().fpe_autotune(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), ws, nb, _stream(stream),
                                   ctypes.byref(c)))
@@ -346,7 +354,7 @@ class Plan:
         e = torch.empty(n, dtype=torch.int64, device=z.device)
         md = torch.empty(n, dtype=torch.complex128, device=z.device)
         ed = torch.empty(n, dtype=torch.int64, device=z.device)
-        ws, nb = self.workspace(n)
+        ws, nb = self.workspace(n, stream)
         _check(lib().fpe_eval_deriv(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
                                     ed.data_ptr(), ws, nb, _stream(stream)))
         return m, e, md, ed
@@ -361,7 +369,7 @@ class Plan:
         md = torch.empty(n, dtype=torch.complex128, device=z.device)
         ed = torch.empty(n, dtype=torch.int64, device=z.device)
         zn = torch.empty(n, dtype=torch.complex128, device=z.device)
-        ws, nb = self.workspace(n)
+        ws, nb = self.workspace(n, stream)
         _check(lib().fpe_newton_step(self._h, z.data_ptr(), n, m.data_ptr(), e.data_ptr(), md.data_ptr(),
                                      ed.data_ptr(), zn.data_ptr(), ws, nb, _stream(stream)))
         return zn, m, e, md, ed
@@ -409,7 +417,7 @@ class Plan:
         if grad_z:
             md = _dev_complex(md, "md")
             ed = ed.contiguous()
-        ws, nb = self.workspace(n)
+        ws, nb = self.workspace(n, stream)
         _check(lib().fpe_eval_adjoint(self._h, z.data_ptr(), n, g.data_ptr(),
                                       g_exp.data_ptr() if g_exp is not None else None,
                                       md.data_ptr() if grad_z else None, ed.data_ptr() if grad_z else None,
@@ -444,8 +452,22 @@ class Batch:
         self._destroy = L.fpe_batch_destroy
         enb = ctypes.c_size_t()
         _check(L.fpe_eval_batched_workspace_size(h, ctypes.byref(enb)))
-        self._eval_buf, self._eval_ws = _workspace(enb.value, self.device)
         self._eval_nb = enb.value
+        self._eval_ws = {}
+        self.eval_workspace(stream)
+
+    def eval_workspace(self, stream=None) -> int:
+        """The evaluation workspace for calls on this stream (one per stream:
+        calls on different streams may overlap)."""
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        key = int(s.cuda_stream)
+        if key not in self._eval_ws:
+            buf, ptr = _workspace(self._eval_nb, self.device)
+            if s != torch.cuda.current_stream():
+                buf.record_stream(s)
+            self._eval_ws[key] = (buf, ptr)
+        return self._eval_ws[key][1]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -466,8 +488,9 @@ class Batch:
         m = torch.empty(n, dtype=torch.complex128, device=z.device)
         e = torch.empty(n, dtype=torch.int64, device=z.device)
         c = ctypes.c_int32()
-        _check(lib().fpe_batch_autotune(self._h, z.data_ptr(), m.data_ptr(), e.data_ptr(), self._eval_ws,
-                                        self._eval_nb, _stream(stream), ctypes.byref(c)))
+        _check(lib().fpe_batch_autotune(self._h, z.data_ptr(), m.data_ptr(), e.data_ptr(),
+                                        self.eval_workspace(stream), self._eval_nb, _stream(stream),
+                                        ctypes.byref(c)))
         return c.value
 
     def eval(self, z, terms: bool = False, out=None, stream=None):
@@ -484,8 +507,8 @@ class Batch:
             m, e = out
         t = torch.empty(n, dtype=torch.int32, device=z.device) if terms else None
         _check(lib().fpe_eval_batched(self._h, z.data_ptr(), m.data_ptr(), e.data_ptr(),
-                                      t.data_ptr() if t is not None else None, self._eval_ws, self._eval_nb,
-                                      _stream(stream)))
+                                      t.data_ptr() if t is not None else None, self.eval_workspace(stream),
+                                      self._eval_nb, _stream(stream)))
         return (m, e, t) if terms else (m, e)
 
 
