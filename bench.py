@@ -19,6 +19,9 @@ Besides the JSON fields the driver reads, the line carries:
                 point, on the host's threads (at most 16) and on one thread;
                 its double-double mode on a sample beside it
   horner_gpu    the same-GPU Horner baseline over all points
+  two_streams   the same evaluations queued alternately on two HIP streams
+                (one plan, a workspace per stream): throughput beside the
+                one-stream headline value
   max_scaled_err  max |FPE - reference| / sum|a_k||z|^k on a seeded sample,
                 the reference being the oracle's window sum at p = 116
 """
@@ -422,6 +425,38 @@ def batched_leg(fpe, workloads, oracle, np, torch, dev, steps: int) -> dict:
             "window_tflops_kept_terms": 8 * kept / (win_ms * 1e-3) / 1e12}
 
 
+def two_stream_leg(plan, z, out, n, torch, warmup: int, steps: int) -> dict:
+    """The same evaluations queued alternately on two streams (the plan keeps
+    one workspace per stream): one evaluation's latency-bound sort kernels and
+    the window kernel's tail overlap the other's work."""
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    souts = []
+    for s in streams:
+        with torch.cuda.stream(s):
+            souts.append((torch.empty_like(out[0]), torch.empty_like(out[1])))
+    cur = torch.cuda.current_stream()
+
+    def run(k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for s in streams:
+            s.wait_event(e0)
+        for i in range(k):
+            plan.eval(z, out=souts[i % 2], stream=streams[i % 2])
+        for s in streams:
+            cur.wait_stream(s)
+        e1.record(cur)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run(max(warmup, 2))
+    ms = run(steps) / steps
+    same = all(torch.equal(o[0], out[0]) and torch.equal(o[1], out[1]) for o in souts)
+    log(f"two streams: {ms:.3f} ms per evaluation ({n / (ms * 1e-3):.3e} evals/s), results identical: {same}")
+    return {"value": n / (ms * 1e-3), "unit": "evaluations/s", "ms_per_step": ms, "streams": 2, "steps": steps,
+            "results_identical": bool(same)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,6 +470,8 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 (p = 24) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-polynomial leg")
     ap.add_argument("--no-wide", action="store_true", help="skip the d = 2^20 wide-range leg (dense and sparse)")
+    ap.add_argument("--no-two-streams", action="store_true",
+                    help="skip the two-stream measurement (kernel-statistics runs: no overlapping launches)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="chunk length of the tiles (0: autotuned before the timed steps)")
     ap.add_argument("--cpu-sample", type=int, default=131072,
@@ -559,33 +596,8 @@ def main() -> int:
     # one workspace per stream): one evaluation's latency-bound sort kernels and
     # the window kernel's tail overlap the other's work; reported beside the
     # one-stream value, which stays the headline
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    souts = []
-    for s in streams:
-        with torch.cuda.stream(s):
-            souts.append((torch.empty_like(out[0]), torch.empty_like(out[1])))
-    cur = torch.cuda.current_stream()
-
-    def two_stream_run(k):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(cur)
-        for s in streams:
-            s.wait_event(e0)
-        for i in range(k):
-            plan.eval(z, out=souts[i % 2], stream=streams[i % 2])
-        for s in streams:
-            cur.wait_stream(s)
-        e1.record(cur)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1)
-
-    two_stream_run(max(args.warmup, 2))
-    ts_ms = two_stream_run(args.steps) / args.steps
-    same = all(torch.equal(o[0], out[0]) and torch.equal(o[1], out[1]) for o in souts)
-    res["two_streams"] = {"value": n / (ts_ms * 1e-3), "unit": "evaluations/s", "ms_per_step": ts_ms,
-                          "streams": 2, "steps": args.steps, "results_identical": bool(same)}
-    log(f"two streams: {ts_ms:.3f} ms per evaluation ({n / (ts_ms * 1e-3):.3e} evals/s), "
-        f"results identical: {same}")
+    if not args.no_two_streams:
+        res["two_streams"] = two_stream_leg(plan, z, out, n, torch, args.warmup, args.steps)
 
     # accuracy on a seeded sample, against the oracle's wide window sum
     import oracle
