@@ -298,6 +298,28 @@ def test_edge_cases(fpe):
     assert mm.numel() == 0
 
 
+def test_points_at_the_ends_of_the_double_range(fpe):
+    """Subnormal points, the smallest normal and the largest finite values,
+    mixed magnitudes of Re and Im, and points spread over |z| = 2^-1000 ..
+    2^1000: windows and term counts as the oracle's, values within tolerance
+    of its compensated Horner sum."""
+    say("eval points at the ends of the double range")
+    big = np.finfo(np.float64).max
+    tiny = np.finfo(np.float64).tiny
+    special = np.array([5e-324, -5e-324j, 1e-320 + 1e-320j, tiny, -tiny * 1j, big, -big, big * 1j,
+                        complex(big, big), complex(-big, 1e-300), complex(1e-310, big), complex(big, -5e-324),
+                        complex(2.0 ** -1022, 2.0 ** -1074), complex(2.0 ** 1023, -2.0 ** 1000)], complex)
+    rng = np.random.default_rng(23)
+    spread = 2.0 ** rng.uniform(-1000, 1000, 400) * np.exp(1j * rng.uniform(0, 2 * np.pi, 400))
+    z = np.concatenate([special, spread])
+    for cc in (workloads.uniform_coeffs(300, 12), workloads.wide_coeffs(4096, 13)):
+        plan, m, e, t, w = gpu_eval(fpe, cc, z)
+        P = oracle.precondition(cc, 53)
+        assert_windows(P, P.eval(z), w, t)
+        assert_values(m, e, cc, z)
+        assert_normalised(m, e)
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
 def test_ragged_point_counts(fpe, n):
     c = workloads.uniform_coeffs(3000, 4)
