@@ -31,6 +31,12 @@
  *     fpe_eval_batched, fpe_horner_eval) only enqueues kernels and returns, so
  *     a HIP graph can capture it once a first call has set the library up on
  *     the device (occupancy queries).
+ *   - Evaluations keep no state in the plan or batch: calls on different
+ *     streams may overlap as long as each has a workspace of its own.  Calls
+ *     that share a workspace (or fpe_eval_noalloc's static one) must not
+ *     overlap.  The tuning setters (fpe_plan_set_*, fpe_batch_set_chunk,
+ *     the autotuners) change the plan or batch for later calls and must not
+ *     run concurrently with calls that use it.
  */
 #ifndef FPE_H
 #define FPE_H
