@@ -8,7 +8,7 @@ over all points (the whole evaluation phase: plan, sort, window sums, combine),
 with the plan and the points resident in HBM.  Preconditioning is timed
 separately, as the paper does.
 
-Besides the JSON fields the driver reads, the line carries:
+Besides the metric, value and timing fields, the line carries:
   roofline      the window kernel (the dominant kernel) against the FP64 vector
                 peak: algorithmic flops per launch / its average launch time
                 from HIP events recorded around it on its stream; traffic is
@@ -483,7 +483,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only: this build evaluates on a single MI355X "
+        print(f"bench.py measures one GPU only: the library evaluates on a single MI355X "
               f"(--gpus {args.gpus}, WORLD_SIZE {world} requested); run with --gpus 1", file=sys.stderr)
         return 2
 
@@ -639,7 +639,7 @@ def main() -> int:
     if not args.no_cpu:
         # the oracle's plain-FP64 window sum (its plan in FP64, z^l by binary
         # powering, Horner's rule over the window) over every point, on the
-        # host's threads (at most 16, the GPU machine's CPU share) and on one
+        # host's threads (at most 16) and on one
         # thread; its double-double mode (the parity reference) on a sample
         threads = oracle.default_threads()
         cplan = oracle.precondition(wl.coeffs, wl.p_bits)
