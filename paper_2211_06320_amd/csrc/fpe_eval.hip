@@ -40,11 +40,13 @@
 // for P(z), an upper bound of the cancelled bits c of eq. (def_prec_loss).
 //
 // Every chunk partial is computed the same way whichever wavefront runs it and
-// fixed-point sums are exact, so results do not depend on the partition or on
-// which points share a wavefront.  The paper only suggests ordering points by
-// |z| and evaluating points of similar size together (Section 1; Section 8.1
-// on parallelisation); here the order is what lets a wavefront read one
-// coefficient per step for all of its lanes.
+// fixed-point sums are exact, so FP64 results do not depend on the partition or
+// on which points share a wavefront.  (With an FP32 table, which part of a tile
+// runs FP32 blocks depends on the tile's other lanes, so those last bits vary
+// with the order the sort leaves open, within the FP32 bound.)  The paper only
+// suggests ordering points by |z| and evaluating points of similar size
+// together (Section 1; Section 8.1 on parallelisation); here the order is what
+// lets a wavefront read one coefficient per step for all of its lanes.
 #include <algorithm>
 #include <climits>
 #include <map>
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(1024) void k_scan_table(EvalWs W) {
 // its rank within that entry.  Each workgroup first scans the table-scan
 // segment totals in LDS (at most kBins + 1 of them); workgroup 0 also stores
 // them, and their sum, for the later kernels.  Points of a bin that share a
-// sort block land in an unspecified order; results do not depend on it.
+// sort block land in an unspecified order; FP64 results do not depend on it.
 __global__ __launch_bounds__(1024) void k_scatter(int n, const double2 *__restrict__ z, EvalWs W) {
     __shared__ int32_t s_boff[kSeg];
     const int nseg = (kBins + 1 + W.tab_ib - 1) / W.tab_ib;
@@ -501,7 +503,7 @@ constexpr int kBatchScanPer = (kBins + 1 + kBatchThreads - 1) / kBatchThreads;  
 // k_bounds, with its own cover in LDS), their order by lambda bin (a counting
 // sort in LDS: a point's rank within its bin from an LDS counter, then a scan
 // of the bin counts; finished points have the bin kBins and come last; the
-// order within a bin is free, since results do not depend on which points
+// order within a bin is free, since FP64 results do not depend on which points
 // share a wavefront) and its slots of the sorted records: the records in that
 // order, then records without a window up to a whole number of groups, so
 // that no group mixes two polynomials.
@@ -980,16 +982,17 @@ __device__ __forceinline__ Z32 make_z32(double zr, double zi) {
 }
 
 // the FP32 recurrence of one block of L coefficients from A (a_{kt - L + 1}
-// .. a_{kt}, interleaved), from the top; lanes above their part add 0 (their
-// recurrence stays 0 until the part starts).  Returns the block's sum h (and
-// with D its derivative d) as doubles.
-template <bool D, bool COMP, int L>
-__device__ __forceinline__ void block32(const float *A, int kt, int hi, bool masked, const Z32 &z, double &br,
+// .. a_{kt}, interleaved), from the top; with MASKED, lanes above their part
+// add 0 (their recurrence stays 0 until the part starts), without it every
+// lane takes every step and the coefficients stay wave-uniform operands.
+// Returns the block's sum h (and with D its derivative d) as doubles.
+template <bool D, bool COMP, int L, bool MASKED>
+__device__ __forceinline__ void block32(const float *A, int kt, int hi, const Z32 &z, double &br,
                                         double &bi, double &dr, double &di) {
     float hr = 0.0f, hh = 0.0f, cr = 0.0f, ch = 0.0f, gr = 0.0f, gh = 0.0f;
 #pragma unroll
     for (int s2 = L - 1; s2 >= 0; --s2) {
-        const bool on = !masked || kt - (L - 1 - s2) <= hi;
+        const bool on = !MASKED || kt - (L - 1 - s2) <= hi;
         const float ar = on ? A[2 * s2] : 0.0f, ai = on ? A[2 * s2 + 1] : 0.0f;
         if constexpr (D) {
             const float tr = fmaf(-gh, z.i, hr), ti = fmaf(gr, z.i, hh);
@@ -1047,7 +1050,8 @@ __device__ __forceinline__ void run_f32(Acc<D> &acc, const Z32 &z, const_table32
 #pragma unroll
         for (int q = 0; q < 2 * kBlock32; ++q) A[q] = p[q];
         double br, bi, dr, di;
-        block32<D, COMP, kBlock32>(A, k, hi, k > ktop, z, br, bi, dr, di);
+        if (k > ktop) block32<D, COMP, kBlock32, true>(A, k, hi, z, br, bi, dr, di);
+        else block32<D, COMP, kBlock32, false>(A, k, hi, z, br, bi, dr, di);
         if constexpr (D) {
             const double nr = fma(Dr, z.z8r, fma(-Di, z.z8i, fma(Hr, z.z7r, fma(-Hi, z.z7i, dr))));
             Di = fma(Dr, z.z8i, fma(Di, z.z8r, fma(Hr, z.z7i, fma(Hi, z.z7r, di))));
