@@ -708,6 +708,8 @@ constexpr int kFinalShort = 8;
 constexpr int kLongPiece = 32;
 constexpr int kLongLds = 2048;        // long groups the finalize kernel holds in LDS
 __host__ __device__ inline int long_cap(int64_t n_waves) { return (int)(n_waves / kFinalShort + 1); }
+// pieces of a long group (group, first owner, last owner)
+__device__ __forceinline__ int long_pieces(int4 v) { return (v.z - v.y + kLongPiece) / kLongPiece; }
 
 // window wavefront w's first tile (its share of the work starts at
 // ceil(w total / NW)), and the split-group list entry of the group it starts in
@@ -784,8 +786,10 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
             const int2 gw = make_int2((int)div_floor(A * NW, total), (int)div_floor((B - gc.last) * NW, total));
             if (gw.y - gw.x >= kFinalShort) {
                 const int li = atomicAdd(W.ctl + 9, 1);
-                W.lgroups[li] = make_int4(g, gw.x, gw.y, 0);
-                s_li[atomicAdd(&s_nl, 1)] = li;
+                const int4 lg = make_int4(g, gw.x, gw.y, 0);
+                W.lgroups[li] = lg;
+                // only a group summed in several pieces uses an accumulator
+                if (long_pieces(lg) > 1) s_li[atomicAdd(&s_nl, 1)] = li;
             }
         }
     } else if (i <= (int64_t)G + NW) {
@@ -793,7 +797,7 @@ __global__ __launch_bounds__(1024) void k_partition(DevPlan P, EvalWs W) {
     }
     __syncthreads();
     // the finalize kernel's accumulators and piece count of each long group
-    // found here start at zero
+    // of several pieces found here start at zero
     const int nl = s_nl;
     for (int k = threadIdx.x; k < nl * (kWave * kSlotWords / 2); k += blockDim.x) {
         const int li = s_li[k / (kWave * kSlotWords / 2)];
@@ -1620,10 +1624,10 @@ void k_window(DevPlan P, double2 *__restrict__ m_out,
 // holds the group in its slot 1, every later owner in its slot 0.  Work items
 // of the grid's wavefronts: the short split groups k_partition listed (one
 // wavefront sums all owners), then the pieces of the long groups (a wavefront
-// sums kLongPiece owners and adds them to the group's accumulator with
-// device-scope atomics; the piece that arrives last writes the outputs).  A
-// long group's slots, up to one per window wavefront, are so read by many
-// compute units at once.
+// sums kLongPiece owners; a group of several pieces adds them to its
+// accumulator with device-scope atomics, and the piece that arrives last
+// writes the outputs).  A long group's slots, up to one per window
+// wavefront, are so read by many compute units at once.
 constexpr int kFinalThreads = 256;
 constexpr int kFinalBlocks = 4096;    // workgroups of the finalize grid, at most
 constexpr int kLongPer = kLongLds / kFinalThreads;   // long groups per thread in the piece scan
@@ -1680,8 +1684,6 @@ __device__ __forceinline__ void add_slots(const EvalWs &W, int wx, int wy, int w
             a[2 * k + 1] += x[u][k].y;
         }
 }
-
-__device__ __forceinline__ int long_pieces(int4 v) { return (v.z - v.y + kLongPiece) / kLongPiece; }
 
 template <bool D, bool B>
 __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P, double2 *__restrict__ m_out,
@@ -1771,9 +1773,10 @@ __global__ __launch_bounds__(kFinalThreads, D ? 4 : 7) void k_finalize(DevPlan P
         long long a[kAccWords] = {};
         for (int w0 = wa; w0 <= wb; w0 += 4) add_slots<kAccWords, 4>(W, wx, wb, w0, lane, a);
         bool last = true;
-        if (li >= 0) {
-            // a piece of a long group: its sums go to the group's accumulator;
-            // the piece that arrives last writes the outputs
+        if (np > 1) {
+            // one of several pieces of a long group: its sums go to the
+            // group's accumulator; the piece that arrives last writes the
+            // outputs (a group of one piece writes them at once)
             unsigned long long *acc =
                 reinterpret_cast<unsigned long long *>(W.lacc) + ((size_t)li * kWave + lane) * kSlotWords;
 #pragma unroll

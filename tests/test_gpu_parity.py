@@ -195,6 +195,38 @@ def test_window_starts_across_chunks(fpe):
     say(f"  max scaled error {worst:.3e}")
 
 
+def test_groups_split_over_many_wavefronts(fpe):
+    """Groups whose tiles are spread over many window wavefronts, in one
+    evaluation at d = 2^16: points on |z| = 1 (windows of the whole polynomial,
+    128 chunks of 512: each group about 1e5 Horner steps against a share of
+    about 150, so hundreds of owners and several pieces summed in the group's
+    accumulator), points with |lambda| log-uniform in [0.002, 0.2] (windows
+    of about 400 to 37000 terms: groups of a few to a few hundred owners,
+    among them the long groups of one piece) and spherical points (short
+    split groups).  Windows at every point, values against the oracle's
+    double-double window sums at p = 116."""
+    d = 1 << 16
+    c = workloads.uniform_coeffs(d, 23)
+    rng = np.random.default_rng(9)
+    on = np.exp(1j * rng.uniform(0, 2 * np.pi, 192))
+    lam = np.exp(rng.uniform(np.log(0.002), np.log(0.2), 1280)) * rng.choice([-1.0, 1.0], 1280)
+    near = 2.0 ** lam * np.exp(1j * rng.uniform(0, 2 * np.pi, 1280))
+    z = np.concatenate([on, near, workloads.spherical_points(8000, 6)])
+    say(f"eval split groups d={d} n={len(z)}")
+    plan, m, e, t, w = gpu_eval(fpe, c, z)
+    chunk = plan.info().chunk
+    span = w[:, 1] // chunk - w[:, 0] // chunk
+    assert (span[:192] >= d // chunk - 1).all()
+    assert (span[192:1472] >= 8).sum() > 400 and (span[192:1472] >= 32).sum() > 100
+    assert_normalised(m, e)
+    P = oracle.precondition(c, 53)
+    assert_windows(P, P.eval(z), w, t)
+    wide = oracle.precondition(c, 116).eval(z)
+    err = oracle.scaled_error(m, e, wide["m"], wide["e"], wide["dwin_m"], wide["dwin_e"])
+    say(f"  max scaled error vs wide window {err.max():.3e}")
+    assert err.max() <= TOL
+
+
 @pytest.mark.parametrize("kind", ["wide", "sparse_wide"])
 def test_wide_dynamic_range(fpe, kind):
     """|a_k| = 2^g, g ~ N(0, 40^2), dense and 1 % sparse: a cover with many slopes."""
