@@ -6,7 +6,9 @@ coefficients i.i.d. uniform on [-1, 1], evaluated at 10^6 points uniform on the
 Riemann sphere (seeded, synthetic), FP64, p = 53.  A step is one fpe_eval call
 over all points (the whole evaluation phase: plan, sort, window sums, combine),
 with the plan and the points resident in HBM.  Preconditioning is timed
-separately, as the paper does.
+separately, as the paper does.  value and ms_per_step: K steps queued back to
+back between two events, right after the W warm-up steps; ms_per_step_median:
+K further steps with an event after each (and the window kernel's events).
 
 Besides the metric, value and timing fields, the line carries:
   roofline      the window kernel (the dominant kernel) against the FP64 vector
